@@ -1,0 +1,267 @@
+"""Plain FP64 CPU oracle for the Wilson-clover operator and its CG solve.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the GPU library ``paper_2503_16994_amd`` and never imports it.
+
+The arithmetic lives in ``lqcd_oracle.c`` (see its header for the operator
+definition and conventions).  This module loads it with ctypes and adds
+the even-odd (Schur complement) pieces as plain compositions of the full
+operator, using ``numpy.linalg`` for the 12x12 site-block inverses.
+
+Conventions (paper Sec. 2.1 and Sec. 3.3; the formula itself is the
+Sheikholeslami-Wohlert operator the paper cites):
+
+* lattice extents ``L = (Lx, Ly, Lz, T)``, time last;
+* canonical arrays: ``U[t, z, y, x, mu, a, b]``, ``psi[t, z, y, x, alpha, a]``;
+* ``kappa`` maps to the bare mass ``m0 = 1/(2 kappa) - 4``;
+* boundary types ``PERIODIC = 0``, ``SF = 1``, ``OPEN = 2``.
+
+Functions with a pin in ``tests/test_oracle_pins.py``: ``gamma``,
+``field_strength``, ``clover_matrix``, ``hop``, ``dw``, ``dw_dag``, ``cg``,
+``schur_*``.  None is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+PERIODIC, SF, OPEN = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lqcd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP over sites, strict FP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        lib.or_field_strength.argtypes = [P, I, P, P]
+        lib.or_clover_matrix.argtypes = [P, I, P, D, D, D, P]
+        lib.or_hop.argtypes = [P, I, P, P, P, P, P]
+        lib.or_dw.argtypes = [P, I, P, P, P, P, P, P]
+        lib.or_dw_dag.argtypes = [P, I, P, P, P, P, P, P]
+        lib.or_gamma.argtypes = [I, P]
+        lib.or_cg.argtypes = [P, I, P, P, P, P, P, P, D, I, P, P]
+        lib.or_cg.restype = I
+        lib.or_cg_fixed.argtypes = [P, I, P, P, P, P, P, P, I]
+        lib.or_cg_fixed.restype = D
+        lib.or_num_threads.restype = I
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _Larr(L):
+    return np.ascontiguousarray(np.asarray(L, dtype=np.int32))
+
+
+def _theta(theta):
+    th = np.ones(4, dtype=np.complex128) if theta is None else np.asarray(theta, np.complex128)
+    return np.ascontiguousarray(th.real), np.ascontiguousarray(th.imag)
+
+
+def _c128(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def m0_from_kappa(kappa: float) -> float:
+    """Bare mass from the hopping parameter, m0 = 1/(2 kappa) - 4."""
+    return 1.0 / (2.0 * kappa) - 4.0
+
+
+def num_threads() -> int:
+    return _load().or_num_threads()
+
+
+def gamma(mu: int) -> np.ndarray:
+    """Chiral-basis gamma matrix (mu = 0..3 for x,y,z,t; 4 for gamma_5)."""
+    g = np.zeros((4, 4), np.complex128)
+    _load().or_gamma(mu, _ptr(g))
+    return g
+
+
+def field_strength(L, bc, U) -> np.ndarray:
+    """Clover field strength F[t,z,y,x,plane,3,3]; planes xy,xz,xt,yz,yt,zt."""
+    U = _c128(U)
+    Lx, Ly, Lz, T = L
+    F = np.zeros((T, Lz, Ly, Lx, 6, 3, 3), np.complex128)
+    _load().or_field_strength(_ptr(_Larr(L)), bc, _ptr(U), _ptr(F))
+    return F
+
+
+def clover_matrix(L, bc, U, m0, csw, cF=1.0) -> np.ndarray:
+    """Diagonal term A(x) as 12x12 matrices, A[t,z,y,x,12,12]."""
+    U = _c128(U)
+    Lx, Ly, Lz, T = L
+    A = np.zeros((T, Lz, Ly, Lx, 12, 12), np.complex128)
+    _load().or_clover_matrix(_ptr(_Larr(L)), bc, _ptr(U), m0, csw, cF, _ptr(A))
+    return A
+
+
+def hop(L, bc, theta, U, psi) -> np.ndarray:
+    """Off-diagonal (hopping) part of Dw applied to psi."""
+    U, psi = _c128(U), _c128(psi)
+    out = np.zeros_like(psi)
+    tr, ti = _theta(theta)
+    _load().or_hop(_ptr(_Larr(L)), bc, _ptr(tr), _ptr(ti), _ptr(U), _ptr(psi), _ptr(out))
+    return out
+
+
+def dw(L, bc, theta, U, A, psi) -> np.ndarray:
+    """Full Wilson-clover operator Dw psi (paper Sec. 3.3, Dw!)."""
+    U, A, psi = _c128(U), _c128(A), _c128(psi)
+    out = np.zeros_like(psi)
+    tr, ti = _theta(theta)
+    _load().or_dw(_ptr(_Larr(L)), bc, _ptr(tr), _ptr(ti), _ptr(U), _ptr(A), _ptr(psi), _ptr(out))
+    return out
+
+
+def dw_dag(L, bc, theta, U, A, psi) -> np.ndarray:
+    """Dw^+ psi = g5 Dw g5 psi."""
+    U, A, psi = _c128(U), _c128(A), _c128(psi)
+    out = np.zeros_like(psi)
+    tr, ti = _theta(theta)
+    _load().or_dw_dag(_ptr(_Larr(L)), bc, _ptr(tr), _ptr(ti), _ptr(U), _ptr(A), _ptr(psi), _ptr(out))
+    return out
+
+
+def cg(L, bc, theta, U, A, eta, tol, maxiter=100000):
+    """CG on the normal equations (paper Sec. 3.3, CG!/propagator!).
+
+    Returns (psi, rho, iters, converged) with rho the true relative residual
+    |eta - Dw psi| / |eta|.
+    """
+    U, A, eta = _c128(U), _c128(A), _c128(eta)
+    psi = np.zeros_like(eta)
+    tr, ti = _theta(theta)
+    rho = ctypes.c_double(0.0)
+    iters = ctypes.c_int(0)
+    st = _load().or_cg(_ptr(_Larr(L)), bc, _ptr(tr), _ptr(ti), _ptr(U), _ptr(A), _ptr(eta),
+                       _ptr(psi), float(tol), int(maxiter), ctypes.byref(rho), ctypes.byref(iters))
+    return psi, rho.value, iters.value, st == 0
+
+
+def cg_fixed(L, bc, theta, U, A, eta, niter):
+    """Exactly ``niter`` CG iterations from zero; returns (psi, |r|/|b|)."""
+    U, A, eta = _c128(U), _c128(A), _c128(eta)
+    psi = np.zeros_like(eta)
+    tr, ti = _theta(theta)
+    rel = _load().or_cg_fixed(_ptr(_Larr(L)), bc, _ptr(tr), _ptr(ti), _ptr(U), _ptr(A),
+                              _ptr(eta), _ptr(psi), int(niter))
+    return psi, rel
+
+
+# --------------------------------------------------------------------------
+# Even-odd pieces, composed from the full operator.
+#
+# With parity p(x) = (x+y+z+t) mod 2 the operator splits into blocks
+#   Dw = [[A_ee, D_eo], [D_oe, A_oo]]
+# where A is the site-diagonal term and D the hopping term.  The Schur
+# complement on the even sites is  Dhat = A_ee - D_eo A_oo^{-1} D_oe.
+# --------------------------------------------------------------------------
+
+def parity_mask(L) -> np.ndarray:
+    """Boolean [t,z,y,x] array, True on odd sites."""
+    Lx, Ly, Lz, T = L
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Lz), np.arange(Ly), np.arange(Lx),
+                             indexing="ij")
+    return ((x + y + z + t) % 2) == 1
+
+
+def _restrict(psi, mask):
+    out = np.zeros_like(psi)
+    out[mask] = psi[mask]
+    return out
+
+
+def apply_blocks(A, psi) -> np.ndarray:
+    """Site-diagonal A(x) psi(x)."""
+    sh = psi.shape
+    v = psi.reshape(sh[:4] + (12,))
+    return np.einsum("...rc,...c->...r", A, v).reshape(sh)
+
+
+def inverse_blocks(A) -> np.ndarray:
+    """A(x)^{-1} per site via numpy.linalg.inv on the 12x12 blocks."""
+    return np.linalg.inv(A)
+
+
+def schur_hop_eo(L, bc, theta, U, Ainv, psi_e) -> np.ndarray:
+    """A_oo^{-1} D_oe psi_e (input: field supported on even sites)."""
+    odd = parity_mask(L)
+    h = hop(L, bc, theta, U, _restrict(psi_e, ~odd))
+    return _restrict(apply_blocks(Ainv, h), odd)
+
+
+def schur_dhat(L, bc, theta, U, A, Ainv, psi_e) -> np.ndarray:
+    """Dhat psi_e = A_ee psi_e - D_eo A_oo^{-1} D_oe psi_e, even-site output."""
+    odd = parity_mask(L)
+    pe = _restrict(psi_e, ~odd)
+    t = schur_hop_eo(L, bc, theta, U, Ainv, pe)
+    out = apply_blocks(A, pe) - hop(L, bc, theta, U, t)
+    out = _restrict(out, ~odd)
+    if bc == SF:
+        out[0] = 0.0
+    return out
+
+
+def schur_source(L, bc, theta, U, Ainv, eta) -> np.ndarray:
+    """eta_hat_e = eta_e - D_eo A_oo^{-1} eta_o."""
+    odd = parity_mask(L)
+    t = _restrict(apply_blocks(Ainv, _restrict(eta, odd)), odd)
+    out = _restrict(eta, ~odd) - _restrict(hop(L, bc, theta, U, t), ~odd)
+    if bc == SF:
+        out[0] = 0.0
+    return out
+
+
+def schur_reconstruct(L, bc, theta, U, Ainv, eta, psi_e) -> np.ndarray:
+    """psi = psi_e + A_oo^{-1} (eta_o - D_oe psi_e) on the odd sites."""
+    odd = parity_mask(L)
+    pe = _restrict(psi_e, ~odd)
+    rhs = _restrict(eta, odd) - _restrict(hop(L, bc, theta, U, pe), odd)
+    po = _restrict(apply_blocks(Ainv, rhs), odd)
+    out = pe + po
+    if bc == SF:
+        out[0] = 0.0
+    return out
+
+
+def dense_dw(L, bc, theta, U, A) -> np.ndarray:
+    """Dw as a dense (12V x 12V) matrix, column j = Dw e_j (tiny lattices)."""
+    Lx, Ly, Lz, T = L
+    n = Lx * Ly * Lz * T * 12
+    M = np.zeros((n, n), np.complex128)
+    e = np.zeros((T, Lz, Ly, Lx, 4, 3), np.complex128)
+    flat = e.reshape(-1)
+    for j in range(n):
+        flat[j] = 1.0
+        M[:, j] = dw(L, bc, theta, U, A, e).reshape(-1)
+        flat[j] = 0.0
+    return M
