@@ -1,0 +1,216 @@
+/*
+ * lqcd.h -- C ABI of the MI355X (gfx950) Wilson-clover library.
+ *
+ * The library applies the O(a)-improved Wilson-Dirac operator Dw (paper
+ * Sec. 3.3: Dw!, g5Dw!, DwdagDw!, with the clover term precomputed by Csw!)
+ * and solves Dw psi = eta for fermion propagators by conjugate gradient on
+ * the normal equations (paper Sec. 3.3: CG!, propagator!).  Lattice
+ * geometry and boundary conditions follow paper Sec. 2.1 (time is the last
+ * extent; periodic, Schroedinger-functional and open boundaries); the Dirac
+ * parameters follow the DiracParam structure of Sec. 3.3 (bare mass via
+ * kappa, csw, theta boundary phase factors with |theta| = 1, twisted mass
+ * mu, boundary coefficient cF).
+ *
+ * Operator (chiral Euclidean gamma basis, g5 = diag(1,1,-1,-1)):
+ *   (Dw psi)(x) = A(x) psi(x) - 1/2 sum_mu [ ph+ (1-g_mu) U_mu(x) psi(x+mu)
+ *                                        + ph- (1+g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *   A(x) = (4 + m0 + d_bnd(x)(cF-1)) + csw (i/4) sum_{mu!=nu} s_{mu nu} F_{mu nu}(x),
+ *   m0 = 1/(2 kappa) - 4, F the traceless clover-leaf field strength.
+ * Boundary handling: PERIODIC multiplies hops crossing the edge of direction
+ * mu by theta_mu (conj(theta_mu) backwards); SF makes slice t = 0 a
+ * Dirichlet slice (output 0 there, input there ignored, d_bnd = 1 on
+ * t = 1, T-1); OPEN cuts the time hops across the boundary and treats the
+ * links U_t(t = T-1) as zero (d_bnd = 1 on t = 0, T-1).
+ *
+ * Canonical data layout at this boundary (device memory, complex128 =
+ * interleaved pairs of doubles, C order, x fastest):
+ *   gauge  U  [t][z][y][x][mu][a][b]     mu = 0..3 = x,y,z,t
+ *   spinor psi[rhs][t][z][y][x][alpha][a] alpha = spin (chiral basis), a = colour
+ * The internal layout (site-coalesced, even-odd split, per precision) is
+ * opaque; LQCD_LAYOUT_INTERNAL exists so that benchmarks can time the
+ * kernels without layout conversion.
+ *
+ * Ownership: the caller owns every buffer.  The library allocates no device
+ * memory in any entry point: gauge storage and workspaces live in caller
+ * memory whose size the *_bytes() queries return, and the library keeps
+ * pointers into it until the corresponding *_free()/destroy().  Host-side
+ * handles are allocated with malloc and released by *_free().
+ *
+ * Streams: `stream` arguments are hipStream_t values passed as void*; NULL
+ * is the default stream.  Device work is enqueued on that stream; calls
+ * return once their device work is enqueued, except lqcd_solve, which
+ * synchronises the stream (it reads convergence flags) before returning.
+ *
+ * Errors: every entry point returns an LQCD_* status.  Arguments are
+ * validated before any device work; on a validation error nothing is
+ * modified.  lqcd_last_error() returns a thread-local message describing the
+ * last failure on the calling thread.  No C++ exception crosses this ABI.
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+  LQCD_OK = 0,
+  LQCD_PENDING = 1,      /* lqcd_poll: request not finished yet */
+  LQCD_EINVAL = -1,      /* invalid argument (see lqcd_last_error) */
+  LQCD_ENOMEM = -2,      /* caller-provided memory too small */
+  LQCD_EDEVICE = -3,     /* HIP runtime error */
+  LQCD_ENOCONV = -4,     /* solver did not reach tol within maxiter */
+  LQCD_ENUMERIC = -5,    /* NaN/Inf in an input or a singular clover block */
+  LQCD_ENOTFOUND = -6,   /* unknown ticket or gauge id */
+  LQCD_EBUSY = -7,       /* request queue full */
+  LQCD_EUNSUPPORTED = -8 /* valid request this build does not implement */
+};
+
+const char *lqcd_strerror(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *lqcd_last_error(void);
+
+/* ---- geometry (paper Sec. 2.1, SpaceParm) ------------------------------ */
+enum { LQCD_BC_PERIODIC = 0, LQCD_BC_SF = 1, LQCD_BC_OPEN = 2 };
+
+typedef struct lqcd_geom_desc {
+  int32_t L[4];         /* extents x, y, z, t; each even and >= 2 */
+  int32_t bc;           /* LQCD_BC_* */
+  double theta_re[4];   /* boundary phase factors, |theta_mu| = 1 (Sec. 3.3); */
+  double theta_im[4];   /*   theta_t is used only with LQCD_BC_PERIODIC       */
+} lqcd_geom_desc;
+
+typedef struct lqcd_geom lqcd_geom_t;
+
+/* Validates desc (EINVAL: extent odd or < 2, bc unknown, |theta| != 1
+ * beyond 1e-12, SF/OPEN with T < 4) and creates a host-side handle. */
+int lqcd_geom(const lqcd_geom_desc *desc, lqcd_geom_t **out);
+void lqcd_geom_free(lqcd_geom_t *g);
+/* Lattice volume V (number of sites). */
+int64_t lqcd_geom_volume(const lqcd_geom_t *g);
+
+/* ---- precisions --------------------------------------------------------- */
+enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_BF16 = 2 };
+/* Bit masks naming the precisions a gauge field or workspace must hold. */
+enum { LQCD_PM_F64 = 1, LQCD_PM_F32 = 2, LQCD_PM_BF16 = 4 };
+
+/* ---- gauge field (paper Sec. 2.2: device-resident vector_field) -------- */
+typedef struct lqcd_gauge lqcd_gauge_t;
+
+/* Device bytes that lqcd_gauge_create needs for the precisions in pmask
+ * (FP64 is always stored). */
+size_t lqcd_gauge_bytes(const lqcd_geom_t *g, int pmask);
+
+/* Imports the canonical FP64 field U_dev (device memory, read only during
+ * the call's device work) into `mem` (device, >= lqcd_gauge_bytes) in the
+ * internal layout, in FP64 and in the other precisions of pmask (FP32 and
+ * BF16 by round-to-nearest-even).  U is used as given, except that with
+ * LQCD_BC_OPEN the stored U_t(t = T-1) is set to zero.  The handle refers to
+ * g and mem: both must outlive it. */
+int lqcd_gauge_create(const lqcd_geom_t *g, const void *U_dev, int pmask, void *mem,
+                      size_t mem_bytes, void *stream, lqcd_gauge_t **out);
+void lqcd_gauge_free(lqcd_gauge_t *u);
+
+/* ---- workspace (paper Sec. 2.2, DiracWorkspace) ------------------------ */
+typedef struct lqcd_ws lqcd_ws_t;
+
+/* Device bytes of a workspace for solves/applications with up to nrhs
+ * right-hand sides in the precisions of pmask. */
+size_t lqcd_ws_bytes(const lqcd_geom_t *g, int pmask, int nrhs);
+int lqcd_ws_create(const lqcd_geom_t *g, int pmask, int nrhs, void *mem, size_t mem_bytes,
+                   lqcd_ws_t **out);
+void lqcd_ws_free(lqcd_ws_t *w);
+
+/* ---- Dirac parameters (paper Sec. 3.3, DiracParam) --------------------- */
+typedef struct lqcd_dirac {
+  double kappa;  /* hopping parameter > 0; m0 = 1/(2 kappa) - 4 */
+  double csw;    /* Sheikholeslami-Wohlert coefficient */
+  double cF;     /* boundary coefficient (c~_t) for SF/OPEN; 1 = tree level */
+  double mu;     /* twisted mass: must be 0 in this build (EUNSUPPORTED) */
+} lqcd_dirac;
+
+/* Csw! analogue (paper Sec. 3.3): computes the clover term of (u, d) into
+ * the workspace, in FP64 and in the other precisions the workspace holds:
+ * A(x) on every site and A(x)^{-1} on the odd sites (FP64 6x6 LDL^H per
+ * chirality block).  ENUMERIC if a block is numerically singular.  Later
+ * calls with the same (u, d) reuse it; lqcd_dw_apply and lqcd_solve call
+ * this themselves when needed. */
+int lqcd_clover(const lqcd_gauge_t *u, const lqcd_dirac *d, lqcd_ws_t *w, void *stream);
+
+/* ---- operator application (paper Sec. 3.3: Dw!, g5Dw!, DwdagDw!) ------- */
+enum {
+  LQCD_OP_DW = 0,          /* full-lattice Dw */
+  LQCD_OP_DW_DAG = 1,      /* Dw^+ = g5 Dw g5 */
+  LQCD_OP_G5DW = 2,        /* g5 Dw */
+  LQCD_OP_DWDAGDW = 3,     /* Dw^+ Dw */
+  LQCD_OP_SCHUR = 4,       /* Dhat = A_ee - D_eo A_oo^{-1} D_oe on even sites */
+  LQCD_OP_SCHUR_DAG = 5,   /* Dhat^+ = g5 Dhat g5 */
+  LQCD_OP_SCHUR_NORMAL = 6,/* Dhat^+ Dhat */
+  LQCD_OP_HOP_EO = 7,      /* A_oo^{-1} D_oe: even input -> odd output */
+  LQCD_OP_HOP_OE = 8       /* A_ee x_e - D_eo y_o: see lqcd_dw_apply */
+};
+enum { LQCD_LAYOUT_CANON = 0, LQCD_LAYOUT_INTERNAL = 1 };
+
+/* Applies `op` to nrhs spinor fields.  With LQCD_LAYOUT_CANON `in` and `out`
+ * are canonical complex128 full-lattice fields (nrhs stacked); the Schur
+ * operators read the even sites of `in` and write the even sites of `out`
+ * (odd sites set to 0); HOP_EO reads the even sites and writes the odd sites
+ * (even sites set to 0); HOP_OE reads x_e from the even and y_o from the odd
+ * sites of `in` and writes even sites.  With LQCD_LAYOUT_INTERNAL `in` and
+ * `out` are internal-layout vectors of precision `prec` (size from
+ * lqcd_vec_bytes).  `in` and `out` must not overlap.  The clover term is
+ * (re)built in `w` when (u, d) differs from the cached one. */
+int lqcd_dw_apply(const lqcd_gauge_t *u, const lqcd_dirac *d, int op, int prec, int layout,
+                  int nrhs, const void *in, void *out, lqcd_ws_t *w, void *stream);
+
+/* Bytes of one internal-layout vector: nrhs fields on `nparity` (1 or 2)
+ * parities in precision prec. */
+size_t lqcd_vec_bytes(const lqcd_geom_t *g, int prec, int nrhs, int nparity);
+
+/* ---- solver (paper Sec. 3.3: CG!, propagator!) ------------------------- */
+enum {
+  LQCD_SOLVER_CG_FULL = 0, /* CG on Dw^+ Dw over the full lattice */
+  LQCD_SOLVER_CG_EO = 1    /* CG on Dhat^+ Dhat (even-odd preconditioned) */
+};
+
+typedef struct lqcd_solve_params {
+  lqcd_dirac d;
+  int32_t solver;          /* LQCD_SOLVER_* */
+  int32_t inner_prec;      /* LQCD_F64, LQCD_F32 or LQCD_BF16 (CG_EO only) */
+  int32_t reliable_every;  /* mixed precision: an FP64 reliable update at least
+                              every reliable_every iterations (0 selects 100),
+                              besides one whenever |r| has dropped tenfold
+                              since the last update */
+  int32_t maxiter;         /* bound on CG iterations per right-hand side */
+  double tol;              /* target true relative residual |eta-Dw psi|/|eta| */
+  int32_t nrhs;            /* number of right-hand sides solved together */
+  int32_t use_graph;       /* capture iteration chunks in a hipGraph */
+} lqcd_solve_params;
+
+typedef struct lqcd_solve_info {
+  int32_t status;           /* LQCD_OK or LQCD_ENOCONV for this rhs */
+  int32_t iters;            /* CG iterations (applications of the normal op) */
+  int32_t reliable_updates; /* FP64 residual recomputations */
+  int32_t restarts;
+  double true_residual;     /* |eta - Dw psi|/|eta| recomputed in FP64 with the
+                               full-lattice operator after the solve */
+  double seconds;           /* wall time of the whole call */
+} lqcd_solve_info;
+
+/* Solves Dw psi_j = eta_j for j < nrhs.  eta and psi are canonical
+ * complex128 fields on the device (nrhs stacked).  With SF boundaries eta
+ * must vanish on slice t = 0 (EINVAL otherwise).  Returns LQCD_OK if every
+ * rhs reached tol, LQCD_ENOCONV otherwise (psi then holds the last
+ * iterates and info[] the residuals reached).  info must hold nrhs
+ * entries. */
+int lqcd_solve(const lqcd_gauge_t *u, const lqcd_solve_params *p, const void *eta,
+               void *psi, lqcd_ws_t *w, void *stream, lqcd_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQCD_H */

@@ -1,0 +1,316 @@
+// CG scalar and vector kernels with the iteration control kept on the device.
+//
+// Every right-hand side carries a CGState.  The recursion (alpha, beta, the
+// fused x/r update) runs in the inner precision; a reliable update
+// (residual recomputed in FP64 from the FP64 solution) is requested by the
+// beta kernel when |r|^2 has dropped below delta^2 times its maximum since the
+// last update, or when it reaches the inner target.  The update kernels run
+// at fixed points of the iteration sequence and skip every rhs that has no
+// pending request, so a captured graph contains them unconditionally.  The
+// update's finish kernel also performs the convergence test on the true
+// residual and marks the rhs done.  The host only polls the done flags.
+#include "lqcd_kernels.h"
+
+namespace lqcd {
+
+constexpr int kB = 256;
+
+__device__ inline double bsum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = sh[0] + sh[1] + sh[2] + sh[3];
+  return s;
+}
+
+// fixed-order sum of n partials, result broadcast to the block
+__device__ inline double psum(const double* p, int n, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kB) acc += p[i];
+  double s = bsum(acc, sh);
+  __shared__ double out;
+  if (threadIdx.x == 0) out = s;
+  __syncthreads();
+  return out;
+}
+
+__device__ inline bool finite(double v) { return v == v && fabs(v) <= 1.7976931348623157e308; }
+
+__global__ void k_cg_setup(CGState* s, const double* b2, const double* eta2, CGSetup cfg) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cfg.nrhs) return;
+  CGState& c = s[r];
+  const double b = b2[r];
+  c.rr = b;
+  c.rr_prev = b;
+  c.rr_max = b;
+  c.pAp = 0.0;
+  c.alpha = 0.0;
+  c.beta = 0.0;
+  c.bnorm2 = b;
+  c.eta2 = eta2[r];
+  c.tol2 = cfg.tol * cfg.tol * eta2[r];
+  c.target2 = cfg.inner_rel * cfg.inner_rel * b;
+  c.delta2 = cfg.delta2;
+  c.rho2 = 1.0;
+  c.iters = 0;
+  c.maxiter = cfg.maxiter;
+  c.rupd = 0;
+  c.restarts = 0;
+  c.inner_hit = 0;
+  c.ru_every = cfg.ru_every;
+  c.last_ru = 0;
+  c.skip_ru = 1;
+  const bool zero = !(b > 0.0) || !(eta2[r] > 0.0);
+  c.done = zero ? 1 : 0;
+  c.status = zero ? CG_CONVERGED : CG_RUNNING;
+  if (zero) c.rho2 = 0.0;
+}
+
+__global__ void k_cg_alpha(CGState* s, const double* partials, int nparts) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x;
+  if (s[r].done) return;
+  const double v = psum(partials + (size_t)r * nparts, nparts, sh);
+  if (threadIdx.x == 0) {
+    CGState& c = s[r];
+    c.pAp = v;
+    c.alpha = (v > 0.0) ? c.rr / v : 0.0;
+  }
+}
+
+__global__ void k_cg_beta(CGState* s, const double* partials, int nparts) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x;
+  if (s[r].done) return;
+  const double v = psum(partials + (size_t)r * nparts, nparts, sh);
+  if (threadIdx.x != 0) return;
+  CGState& c = s[r];
+  c.iters += 1;
+  if (!finite(v) || !finite(c.alpha)) {
+    c.done = 1;
+    c.status = CG_NONFINITE;
+    c.skip_ru = 1;
+    return;
+  }
+  const bool hit = v <= c.target2;
+  const bool due = c.ru_every > 0 && c.iters - c.last_ru >= c.ru_every;
+  if (hit || due || v < c.delta2 * c.rr_max) {
+    c.skip_ru = 0;
+    if (hit) c.inner_hit = 1;
+  }
+  c.beta = (c.rr > 0.0) ? v / c.rr : 0.0;
+  c.rr_prev = c.rr;
+  c.rr = v;
+  if (v > c.rr_max) c.rr_max = v;
+  if (c.iters >= c.maxiter && c.skip_ru) {
+    c.done = 1;
+    c.status = CG_MAXITER;
+  }
+}
+
+// x += alpha p ; r -= alpha Ap ; |r|^2 partials   (x may be wider than r)
+template <typename SX, typename S>
+__global__ void k_cg_xr(SX* x, S* r, const S* __restrict__ p, const S* __restrict__ Ap, long n,
+                        long rsx, long rs, const CGState* cs, double* partials) {
+  __shared__ double sh[4];
+  const int q = blockIdx.y;
+  if (cs[q].done) return;
+  using A = typename StoreTraits<S>::acc;
+  const double alpha_d = cs[q].alpha;
+  const A alpha = (A)alpha_d;
+  const size_t o = (size_t)q * rs, ox = (size_t)q * rsx;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    auto pv = ld(p + o + i);
+    auto av = ld(Ap + o + i);
+    auto xv = ld(x + ox + i);
+    auto rv = ld(r + o + i);
+    using AX = decltype(xv.re);
+    xv.re += (AX)alpha_d * (AX)pv.re;
+    xv.im += (AX)alpha_d * (AX)pv.im;
+    rv.re -= alpha * av.re;
+    rv.im -= alpha * av.im;
+    st(x + ox + i, xv);
+    st(r + o + i, rv);
+    acc += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+  }
+  double b = bsum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)q * gridDim.x + blockIdx.x] = b;
+}
+
+// p = r + beta p ; optional low-precision copy of p
+template <typename S, typename SL>
+__global__ void k_cg_p(S* p, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
+  const int q = blockIdx.y;
+  if (cs[q].done) return;
+  using A = typename StoreTraits<S>::acc;
+  const A beta = (A)cs[q].beta;
+  const size_t o = (size_t)q * rs;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    auto pv = ld(p + o + i);
+    auto rv = ld(r + o + i);
+    pv.re = rv.re + beta * pv.re;
+    pv.im = rv.im + beta * pv.im;
+    st(p + o + i, pv);
+    if (plo) st(plo + o + i, pv);
+  }
+}
+
+__device__ inline bool ru_skip(const CGState& c) { return c.skip_ru != 0 || c.done != 0; }
+
+// reliable update, step 1: fold the low-precision correction into x (FP64)
+__global__ void k_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, const CGState* cs) {
+  const int q = blockIdx.y;
+  if (ru_skip(cs[q])) return;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    float2 a = xl[(size_t)q * rsl + i];
+    double2 b = X[(size_t)q * rsX + i];
+    X[(size_t)q * rsX + i] = make_double2(b.x + (double)a.x, b.y + (double)a.y);
+    xl[(size_t)q * rsl + i] = make_float2(0.f, 0.f);
+  }
+}
+
+// step 2: s = g5 (b - y) with |s|^2 partials (y = Dhat x or Dw x); b, y, s
+// are [rhs][12 * nsp][V2] with spins 2,3 of every parity block negated
+__global__ void k_ru_sub(const double2* __restrict__ b, const double2* __restrict__ y, double2* s, long n,
+                         long rs, long V2, const CGState* cs, double* partials) {
+  __shared__ double sh[4];
+  const int q = blockIdx.y;
+  if (ru_skip(cs[q])) return;
+  const size_t o = (size_t)q * rs;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    double2 u = b[o + i], v = y[o + i];
+    double2 d = make_double2(u.x - v.x, u.y - v.y);
+    acc += d.x * d.x + d.y * d.y;
+    const long k = (i / V2) % 12;  // component index within a parity block
+    if (k >= 6) d = make_double2(-d.x, -d.y);
+    s[o + i] = d;
+  }
+  double t = bsum(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)q * gridDim.x + blockIdx.x] = t;
+}
+
+// step 3 (mixed only): r_lo = (float) r_true
+__global__ void k_ru_copy(const double2* __restrict__ R, long rsR, float2* rl, long rsl, long n,
+                          const CGState* cs) {
+  const int q = blockIdx.y;
+  if (ru_skip(cs[q])) return;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    double2 v = R[(size_t)q * rsR + i];
+    rl[(size_t)q * rsl + i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// step 4: convergence test on the true residual and restart of the recursion
+__global__ void k_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r,
+                            int n_r) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x;
+  if (ru_skip(s[r])) return;
+  const double res2 = psum(part_res + (size_t)r * n_res, n_res, sh);
+  const double rr = psum(part_r + (size_t)r * n_r, n_r, sh);
+  if (threadIdx.x != 0) return;
+  CGState& c = s[r];
+  c.rupd += 1;
+  c.last_ru = c.iters;
+  c.rho2 = res2 / c.eta2;
+  c.skip_ru = 1;
+  if (!finite(res2) || !finite(rr)) {
+    c.done = 1;
+    c.status = CG_NONFINITE;
+    return;
+  }
+  if (res2 <= c.tol2) {
+    c.done = 1;
+    c.status = CG_CONVERGED;
+    return;
+  }
+  if (c.inner_hit) {  // inner target reached without the true one: tighten it
+    c.target2 *= 0.01;
+    c.restarts += 1;
+    c.inner_hit = 0;
+  }
+  // the recursion continues from the true residual (p is kept)
+  c.rr = rr;
+  c.rr_max = rr;
+  if (c.iters >= c.maxiter) {
+    c.done = 1;
+    c.status = CG_MAXITER;
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_cg_setup(CGState* s, const double* b2, const double* eta2, const CGSetup& cfg,
+                           hipStream_t st) {
+  k_cg_setup<<<(cfg.nrhs + 63) / 64, 64, 0, st>>>(s, b2, eta2, cfg);
+  return hipGetLastError();
+}
+hipError_t launch_cg_alpha(CGState* s, const double* partials, int nparts, int nrhs, hipStream_t st) {
+  k_cg_alpha<<<nrhs, kB, 0, st>>>(s, partials, nparts);
+  return hipGetLastError();
+}
+hipError_t launch_cg_beta(CGState* s, const double* partials, int nparts, int nrhs, hipStream_t st) {
+  k_cg_beta<<<nrhs, kB, 0, st>>>(s, partials, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, const void* Ap, int prec,
+                        long n, long rs, int nrhs, const CGState* s, double* partials, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  if (prec == P_F64 && xprec == P_F64)
+    k_cg_xr<double2, double2><<<grid, kB, 0, st>>>((double2*)x, (double2*)r, (const double2*)p,
+                                                   (const double2*)Ap, n, rsx, rs, s, partials);
+  else if (prec == P_F32 && xprec == P_F32)
+    k_cg_xr<float2, float2><<<grid, kB, 0, st>>>((float2*)x, (float2*)r, (const float2*)p,
+                                                 (const float2*)Ap, n, rsx, rs, s, partials);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs, const CGState* s,
+                       void* plo, int lo_prec, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  if (prec == P_F64)
+    k_cg_p<double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
+                                                  (double2*)nullptr);
+  else if (prec == P_F32 && (plo == nullptr || lo_prec == P_F32))
+    k_cg_p<float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo);
+  else if (prec == P_F32 && lo_prec == P_BF16)
+    k_cg_p<float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs, const CGState* s,
+                          hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  k_ru_fold<<<grid, kB, 0, st>>>(X, rsX, xl, rsl, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs, long V2,
+                         int nrhs, const CGState* s, double* partials, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  k_ru_sub<<<grid, kB, 0, st>>>(b, y, s_out, n, rs, V2, s, partials);
+  return hipGetLastError();
+}
+hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
+                          const CGState* s, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  k_ru_copy<<<grid, kB, 0, st>>>(R, rsR, rl, rsl, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r, int n_r,
+                            int nrhs, hipStream_t st) {
+  k_ru_finish<<<nrhs, kB, 0, st>>>(s, part_res, n_res, part_r, n_r);
+  return hipGetLastError();
+}
+
+}  // namespace lqcd

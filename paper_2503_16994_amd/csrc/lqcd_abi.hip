@@ -1,0 +1,495 @@
+// C ABI: handles, validation, gauge import, workspace planning, clover
+// caching and operator application.  Declarations and contracts are in
+// include/lqcd.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <atomic>
+#include <new>
+
+#include "lqcd_internal.h"
+
+using namespace lqcd;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local char g_last_error[512] = "";
+
+namespace lqcd {
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return status;
+}
+}  // namespace lqcd
+
+extern "C" const char* lqcd_last_error(void) { return g_last_error; }
+
+extern "C" const char* lqcd_strerror(int s) {
+  switch (s) {
+    case LQCD_OK: return "ok";
+    case LQCD_PENDING: return "pending";
+    case LQCD_EINVAL: return "invalid argument";
+    case LQCD_ENOMEM: return "memory too small";
+    case LQCD_EDEVICE: return "device error";
+    case LQCD_ENOCONV: return "solver did not converge";
+    case LQCD_ENUMERIC: return "numerical error";
+    case LQCD_ENOTFOUND: return "not found";
+    case LQCD_EBUSY: return "busy";
+    case LQCD_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+extern "C" int lqcd_geom(const lqcd_geom_desc* d, lqcd_geom_t** out) {
+  if (!d || !out) return fail(LQCD_EINVAL, "lqcd_geom: null pointer");
+  *out = nullptr;
+  int64_t V = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (d->L[mu] < 2 || (d->L[mu] & 1))
+      return fail(LQCD_EINVAL, "lqcd_geom: extent L[%d]=%d must be even and >= 2", mu, d->L[mu]);
+    V *= d->L[mu];
+  }
+  if (V >= (int64_t(1) << 31)) return fail(LQCD_EINVAL, "lqcd_geom: volume %lld too large", (long long)V);
+  if (d->bc != LQCD_BC_PERIODIC && d->bc != LQCD_BC_SF && d->bc != LQCD_BC_OPEN)
+    return fail(LQCD_EINVAL, "lqcd_geom: unknown boundary condition %d", d->bc);
+  if (d->bc != LQCD_BC_PERIODIC && d->L[3] < 4)
+    return fail(LQCD_EINVAL, "lqcd_geom: SF/open boundaries need T >= 4");
+  for (int mu = 0; mu < 4; ++mu) {
+    double a = hypot(d->theta_re[mu], d->theta_im[mu]);
+    if (!(fabs(a - 1.0) <= 1e-12))
+      return fail(LQCD_EINVAL, "lqcd_geom: |theta[%d]| = %.17g, must be 1", mu, a);
+  }
+  lqcd_geom_t* g = new (std::nothrow) lqcd_geom_t;
+  if (!g) return fail(LQCD_ENOMEM, "lqcd_geom: host allocation failed");
+  g->desc = *d;
+  g->V = V;
+  g->V2 = (int)(V / 2);
+  KGeom& k = g->kg;
+  memset(&k, 0, sizeof(k));
+  for (int mu = 0; mu < 4; ++mu) k.L[mu] = d->L[mu];
+  k.Lxh = d->L[0] / 2;
+  k.V2 = g->V2;
+  k.sy = k.Lxh;
+  k.sz = k.Lxh * d->L[1];
+  k.st = k.Lxh * d->L[1] * d->L[2];
+  k.bc = d->bc;
+  k.div_xh = make_fastdiv(k.Lxh);
+  k.div_y = make_fastdiv(d->L[1]);
+  k.div_z = make_fastdiv(d->L[2]);
+  for (int mu = 0; mu < 4; ++mu) {
+    double re = d->theta_re[mu], im = d->theta_im[mu];
+    if (mu == 3 && d->bc != LQCD_BC_PERIODIC) re = im = 0.0;  // time hops cut at the boundary
+    k.fwd_re[mu] = re;
+    k.fwd_im[mu] = im;
+    k.bwd_re[mu] = re;
+    k.bwd_im[mu] = -im;
+  }
+  *out = g;
+  return LQCD_OK;
+}
+
+extern "C" void lqcd_geom_free(lqcd_geom_t* g) { delete g; }
+extern "C" int64_t lqcd_geom_volume(const lqcd_geom_t* g) { return g ? g->V : 0; }
+
+// ---------------------------------------------------------------------------
+// gauge field
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static size_t link_elems(const lqcd_geom_t* g) { return (size_t)2 * 4 * 9 * g->V2; }
+
+extern "C" size_t lqcd_gauge_bytes(const lqcd_geom_t* g, int pmask) {
+  if (!g) return 0;
+  size_t b = align_up(link_elems(g) * 16);
+  if (pmask & LQCD_PM_F32) b += align_up(link_elems(g) * 8);
+  if (pmask & LQCD_PM_BF16) b += align_up(link_elems(g) * 4);
+  return b;
+}
+
+static std::atomic<uint64_t> g_uid{1};
+
+extern "C" int lqcd_gauge_create(const lqcd_geom_t* g, const void* U_dev, int pmask, void* mem,
+                                 size_t mem_bytes, void* stream, lqcd_gauge_t** out) {
+  if (!g || !U_dev || !mem || !out) return fail(LQCD_EINVAL, "lqcd_gauge_create: null pointer");
+  *out = nullptr;
+  if (pmask & ~7) return fail(LQCD_EINVAL, "lqcd_gauge_create: bad precision mask %d", pmask);
+  const size_t need = lqcd_gauge_bytes(g, pmask);
+  if (mem_bytes < need)
+    return fail(LQCD_ENOMEM, "lqcd_gauge_create: %zu bytes given, %zu needed", mem_bytes, need);
+  if (((uintptr_t)mem & 255) || ((uintptr_t)U_dev & 15))
+    return fail(LQCD_EINVAL, "lqcd_gauge_create: misaligned device pointer");
+  lqcd_gauge* u = new (std::nothrow) lqcd_gauge;
+  if (!u) return fail(LQCD_ENOMEM, "lqcd_gauge_create: host allocation failed");
+  char* p = (char*)mem;
+  u->g = g;
+  u->pmask = pmask | LQCD_PM_F64;
+  u->uid = g_uid.fetch_add(1);
+  u->U64 = (double2*)p;
+  p += align_up(link_elems(g) * 16);
+  u->U32 = nullptr;
+  u->U16 = nullptr;
+  if (pmask & LQCD_PM_F32) {
+    u->U32 = (float2*)p;
+    p += align_up(link_elems(g) * 8);
+  }
+  if (pmask & LQCD_PM_BF16) {
+    u->U16 = (bf16x2*)p;
+    p += align_up(link_elems(g) * 4);
+  }
+  hipError_t e = launch_import_gauge(g->kg, (const double2*)U_dev, u->U64, u->U32, u->U16,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) {
+    delete u;
+    return hip_status(e, "gauge import");
+  }
+  *out = u;
+  return LQCD_OK;
+}
+
+extern "C" void lqcd_gauge_free(lqcd_gauge_t* u) { delete u; }
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+namespace lqcd {
+
+WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base) {
+  WsLayout m;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* r = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return r;
+  };
+  const size_t V2 = (size_t)g->V2;
+  m.C64 = (double2*)take(72 * V2 * 16);
+  m.Ci64 = (double2*)take(36 * V2 * 16);
+  if (pmask & LQCD_PM_F32) {
+    m.C32 = (float2*)take(72 * V2 * 8);
+    m.Ci32 = (float2*)take(36 * V2 * 8);
+  }
+  if (pmask & LQCD_PM_BF16) {
+    m.C16 = (bf16x2*)take(72 * V2 * 4);
+    m.Ci16 = (bf16x2*)take(36 * V2 * 4);
+  }
+  m.err_flag = (int*)take(256);
+  const size_t full64 = (size_t)nrhs * 24 * V2 * 16;
+  m.E = (double2*)take(full64);
+  m.X = (double2*)take(full64);
+  m.TMP = (double2*)take(full64);
+  m.R = (double2*)take(full64);
+  m.P = (double2*)take(full64);
+  m.Q = (double2*)take(full64);
+  m.AP = (double2*)take(full64);
+  m.EH = (double2*)take(full64);
+  if (pmask & (LQCD_PM_F32 | LQCD_PM_BF16)) {
+    const size_t half32 = (size_t)nrhs * 12 * V2 * 8;
+    m.xl = (float2*)take(half32);
+    m.rl = (float2*)take(half32);
+    m.pl = (float2*)take(half32);
+    m.ql = (float2*)take(half32);
+    m.apl = (float2*)take(half32);
+    m.tl = (float2*)take(half32);
+  }
+  if (pmask & LQCD_PM_BF16) {
+    const size_t half16 = (size_t)nrhs * 12 * V2 * 4;
+    m.pb = (bf16x2*)take(half16);
+    m.qb = (bf16x2*)take(half16);
+    m.tb = (bf16x2*)take(half16);
+  }
+  const int hop_parts = 2 * (int)((V2 + 255) / 256);
+  m.max_parts = hop_parts > 2048 ? hop_parts : 2048;
+  m.partials = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
+  m.partials2 = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
+  m.cg = (CGState*)take((size_t)nrhs * sizeof(CGState));
+  m.scal = (double*)take((size_t)8 * nrhs * sizeof(double));
+  m.bytes = off;
+  return m;
+}
+
+}  // namespace lqcd
+
+extern "C" size_t lqcd_ws_bytes(const lqcd_geom_t* g, int pmask, int nrhs) {
+  if (!g || nrhs < 1) return 0;
+  return plan_ws(g, pmask, nrhs, nullptr).bytes;
+}
+
+extern "C" int lqcd_ws_create(const lqcd_geom_t* g, int pmask, int nrhs, void* mem, size_t mem_bytes,
+                              lqcd_ws_t** out) {
+  if (!g || !mem || !out) return fail(LQCD_EINVAL, "lqcd_ws_create: null pointer");
+  *out = nullptr;
+  if (nrhs < 1 || nrhs > 64) return fail(LQCD_EINVAL, "lqcd_ws_create: nrhs=%d out of range", nrhs);
+  if (pmask & ~7) return fail(LQCD_EINVAL, "lqcd_ws_create: bad precision mask %d", pmask);
+  if ((uintptr_t)mem & 255) return fail(LQCD_EINVAL, "lqcd_ws_create: memory not 256-byte aligned");
+  WsLayout m = plan_ws(g, pmask, nrhs, (char*)mem);
+  if (mem_bytes < m.bytes)
+    return fail(LQCD_ENOMEM, "lqcd_ws_create: %zu bytes given, %zu needed", mem_bytes, m.bytes);
+  lqcd_ws* w = new (std::nothrow) lqcd_ws;
+  if (!w) return fail(LQCD_ENOMEM, "lqcd_ws_create: host allocation failed");
+  w->g = g;
+  w->pmask = pmask | LQCD_PM_F64;
+  w->nrhs = nrhs;
+  w->m = m;
+  *out = w;
+  return LQCD_OK;
+}
+
+extern "C" void lqcd_ws_free(lqcd_ws_t* w) { delete w; }
+
+extern "C" size_t lqcd_vec_bytes(const lqcd_geom_t* g, int prec, int nrhs, int nparity) {
+  if (!g || nrhs < 1 || nparity < 1 || nparity > 2 || prec < 0 || prec > 2) return 0;
+  return (size_t)nrhs * nparity * 12 * g->V2 * elem_bytes(prec);
+}
+
+// ---------------------------------------------------------------------------
+// clover (Csw!)
+// ---------------------------------------------------------------------------
+namespace lqcd {
+
+int check_dirac(const lqcd_dirac* d) {
+  if (!d) return fail(LQCD_EINVAL, "null Dirac parameters");
+  if (!(d->kappa > 0.0) || !isfinite(d->kappa)) return fail(LQCD_EINVAL, "kappa must be > 0");
+  if (!isfinite(d->csw) || !isfinite(d->cF)) return fail(LQCD_EINVAL, "csw and cF must be finite");
+  if (d->mu != 0.0) return fail(LQCD_EUNSUPPORTED, "twisted mass mu != 0 is not implemented");
+  return LQCD_OK;
+}
+
+int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipStream_t st) {
+  int rc = check_dirac(d);
+  if (rc) return rc;
+  if (u->g != w->g && memcmp(&u->g->desc, &w->g->desc, sizeof(lqcd_geom_desc)) != 0)
+    return fail(LQCD_EINVAL, "gauge field and workspace have different geometries");
+  const int want = w->pmask & u->pmask;
+  if (w->clover_valid && w->clover_uid == u->uid && w->kappa == d->kappa && w->csw == d->csw &&
+      w->cF == d->cF && (w->clover_pmask & want) == want)
+    return LQCD_OK;
+  CloverLaunch c;
+  c.g = w->g->kg;
+  c.U64 = u->U64;
+  c.m0 = 1.0 / (2.0 * d->kappa) - 4.0;
+  c.csw = d->csw;
+  c.cF = d->cF;
+  c.C64 = w->m.C64;
+  c.Ci64 = w->m.Ci64;
+  c.C32 = (want & LQCD_PM_F32) ? w->m.C32 : nullptr;
+  c.Ci32 = (want & LQCD_PM_F32) ? w->m.Ci32 : nullptr;
+  c.C16 = (want & LQCD_PM_BF16) ? w->m.C16 : nullptr;
+  c.Ci16 = (want & LQCD_PM_BF16) ? w->m.Ci16 : nullptr;
+  c.err_flag = w->m.err_flag;
+  LQCD_HIP(launch_fill_zero(w->m.err_flag, 256, st));
+  LQCD_HIP(launch_clover(c, st));
+  int err = 0;
+  LQCD_HIP(hipMemcpyAsync(&err, w->m.err_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  LQCD_HIP(hipStreamSynchronize(st));
+  w->clover_valid = false;
+  if (err) return fail(LQCD_ENUMERIC, "clover block numerically singular (kappa=%g csw=%g)", d->kappa, d->csw);
+  w->clover_valid = true;
+  w->clover_uid = u->uid;
+  w->kappa = d->kappa;
+  w->csw = d->csw;
+  w->cF = d->cF;
+  w->clover_pmask = want | LQCD_PM_F64;
+  return LQCD_OK;
+}
+
+}  // namespace lqcd
+
+extern "C" int lqcd_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, void* stream) {
+  if (!u || !d || !w) return fail(LQCD_EINVAL, "lqcd_clover: null pointer");
+  return ensure_clover(u, d, w, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// operator application
+// ---------------------------------------------------------------------------
+namespace lqcd {
+
+struct OpCtx {
+  const lqcd_gauge* u;
+  lqcd_ws* w;
+  int prec;
+  int nrhs;
+  hipStream_t st;
+};
+
+static const void* links_of(const lqcd_gauge* u, int prec) {
+  return prec == P_F64 ? (const void*)u->U64 : (prec == P_F32 ? (const void*)u->U32 : (const void*)u->U16);
+}
+static const void* clov_of(const lqcd_ws* w, int prec) {
+  return prec == P_F64 ? (const void*)w->m.C64 : (prec == P_F32 ? (const void*)w->m.C32 : (const void*)w->m.C16);
+}
+static const void* cloi_of(const lqcd_ws* w, int prec) {
+  return prec == P_F64 ? (const void*)w->m.Ci64 : (prec == P_F32 ? (const void*)w->m.Ci32 : (const void*)w->m.Ci16);
+}
+
+static HopLaunch base_launch(const OpCtx& c) {
+  HopLaunch h;
+  memset(&h, 0, sizeof(h));
+  h.g = c.w->g->kg;
+  h.prec = h.in_prec = h.out_prec = c.prec;
+  h.U = links_of(c.u, c.prec);
+  h.nrhs = c.nrhs;
+  h.nr_tile = 1;
+  h.hop = true;
+  return h;
+}
+
+// full-layout element strides
+static long full_rs(const lqcd_geom_t* g) { return 24L * g->V2; }
+static long par_off(const lqcd_geom_t* g) { return 12L * g->V2; }
+
+static char* elem_ptr(void* base, int prec, long elems) {
+  return (char*)base + (size_t)elems * elem_bytes(prec);
+}
+
+// out (full) = Dw y on both parities, optional g5 on the output and partials
+static hipError_t apply_dw_full(const OpCtx& c, const void* y, void* out, bool g5, double* partials) {
+  const lqcd_geom_t* g = c.w->g;
+  HopLaunch h = base_launch(c);
+  h.both = true;
+  h.par_stride = par_off(g);
+  h.cpre_par = 36L * g->V2;
+  h.y = y;
+  h.z = y;
+  h.out = out;
+  h.y_rs = h.z_rs = h.out_rs = full_rs(g);
+  h.Cpre = clov_of(c.w, c.prec);
+  h.pre = PRE_CLOV;
+  h.post = POST_NONE;
+  h.scale = -0.5;
+  h.g5 = g5;
+  h.partials = partials;
+  return launch_hop(h, c.st);
+}
+
+// t_o = A_oo^{-1} D_oe y_e (tmp odd part of `t` full vector)
+static hipError_t apply_hop_eo(const OpCtx& c, const void* y_full, void* t_full) {
+  const lqcd_geom_t* g = c.w->g;
+  HopLaunch h = base_launch(c);
+  h.p_out = 1;
+  h.y = y_full;
+  h.out = elem_ptr(t_full, c.prec, par_off(g));
+  h.y_rs = h.out_rs = full_rs(g);
+  h.Cpost = cloi_of(c.w, c.prec);
+  h.pre = PRE_NONE;
+  h.post = POST_CLOV;
+  h.scale = -0.5;
+  return launch_hop(h, c.st);
+}
+
+// out_e = A_ee z_e + 1/2 H t_o  (= Dhat z when t = A_oo^{-1} D_oe z)
+static hipError_t apply_hop_oe(const OpCtx& c, const void* z_full, const void* t_full, void* out_full,
+                               bool g5, double* partials) {
+  const lqcd_geom_t* g = c.w->g;
+  HopLaunch h = base_launch(c);
+  h.p_out = 0;
+  h.y = elem_ptr((void*)t_full, c.prec, par_off(g));
+  h.z = z_full;
+  h.out = out_full;
+  h.y_rs = h.z_rs = h.out_rs = full_rs(g);
+  h.Cpre = clov_of(c.w, c.prec);
+  h.pre = PRE_CLOV;
+  h.post = POST_NONE;
+  h.scale = 0.5;
+  h.g5 = g5;
+  h.partials = partials;
+  return launch_hop(h, c.st);
+}
+
+}  // namespace lqcd
+
+extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op, int prec, int layout,
+                             int nrhs, const void* in, void* out, lqcd_ws_t* w, void* stream) {
+  if (!u || !d || !in || !out || !w) return fail(LQCD_EINVAL, "lqcd_dw_apply: null pointer");
+  if (op < LQCD_OP_DW || op > LQCD_OP_HOP_OE) return fail(LQCD_EINVAL, "lqcd_dw_apply: bad op %d", op);
+  if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_dw_apply: bad precision %d", prec);
+  if (layout != LQCD_LAYOUT_CANON && layout != LQCD_LAYOUT_INTERNAL)
+    return fail(LQCD_EINVAL, "lqcd_dw_apply: bad layout %d", layout);
+  if (nrhs < 1 || nrhs > w->nrhs) return fail(LQCD_EINVAL, "lqcd_dw_apply: nrhs=%d (workspace %d)", nrhs, w->nrhs);
+  const int pbit = 1 << prec;
+  if (!(u->pmask & pbit) || !(w->pmask & pbit))
+    return fail(LQCD_EINVAL, "lqcd_dw_apply: precision %d not held by gauge field and workspace", prec);
+  if (in == out) return fail(LQCD_EINVAL, "lqcd_dw_apply: in and out must differ");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_clover(u, d, w, st);
+  if (rc) return rc;
+
+  const lqcd_geom_t* g = w->g;
+  OpCtx c{u, w, prec, nrhs, st};
+  // internal-layout operands: caller's memory or workspace FP64 slots reused
+  // as storage of any precision (they are the widest)
+  const void* vin = in;
+  void* vout = out;
+  const bool canon = (layout == LQCD_LAYOUT_CANON);
+  const bool g5in = (op == LQCD_OP_DW_DAG || op == LQCD_OP_SCHUR_DAG);
+  if (canon) {
+    vin = w->m.X;
+    vout = w->m.TMP;
+    LQCD_HIP(launch_pack(g->kg, (const double2*)in, (void*)vin, prec, nrhs, g5in, st));
+  }
+  const size_t full_bytes = (size_t)nrhs * 24 * g->V2 * elem_bytes(prec);
+  void* tmp = w->m.R;  // scratch full vector
+  void* tmp2 = w->m.P;
+  switch (op) {
+    case LQCD_OP_DW:
+    case LQCD_OP_G5DW:
+      LQCD_HIP(apply_dw_full(c, vin, vout, op == LQCD_OP_G5DW, nullptr));
+      break;
+    case LQCD_OP_DW_DAG:
+      if (!canon) {  // g5 on the input of an internal vector: copy with g5
+        LQCD_HIP(hipMemcpyAsync(tmp2, vin, full_bytes, hipMemcpyDeviceToDevice, st));
+        LQCD_HIP(launch_g5(tmp2, prec, g->V2, 12L * g->V2, 2 * nrhs, st));
+        vin = tmp2;
+      }
+      LQCD_HIP(apply_dw_full(c, vin, vout, true, nullptr));
+      break;
+    case LQCD_OP_DWDAGDW:
+      LQCD_HIP(apply_dw_full(c, vin, tmp, true, nullptr));
+      LQCD_HIP(apply_dw_full(c, tmp, vout, true, nullptr));
+      break;
+    case LQCD_OP_SCHUR:
+    case LQCD_OP_SCHUR_DAG:
+      if (op == LQCD_OP_SCHUR_DAG && !canon) {
+        LQCD_HIP(hipMemcpyAsync(tmp2, vin, full_bytes, hipMemcpyDeviceToDevice, st));
+        LQCD_HIP(launch_g5(tmp2, prec, g->V2, 12L * g->V2, 2 * nrhs, st));
+        vin = tmp2;
+      }
+      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      LQCD_HIP(apply_hop_eo(c, vin, tmp));
+      LQCD_HIP(apply_hop_oe(c, vin, tmp, vout, op == LQCD_OP_SCHUR_DAG, nullptr));
+      break;
+    case LQCD_OP_SCHUR_NORMAL:
+      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      LQCD_HIP(launch_fill_zero(tmp2, full_bytes, st));
+      LQCD_HIP(apply_hop_eo(c, vin, tmp));
+      LQCD_HIP(apply_hop_oe(c, vin, tmp, tmp2, true, nullptr));
+      LQCD_HIP(apply_hop_eo(c, tmp2, tmp));
+      LQCD_HIP(apply_hop_oe(c, tmp2, tmp, vout, true, nullptr));
+      break;
+    case LQCD_OP_HOP_EO:
+      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      LQCD_HIP(apply_hop_eo(c, vin, vout));
+      break;
+    case LQCD_OP_HOP_OE: {
+      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      LQCD_HIP(apply_hop_oe(c, vin, vin, vout, false, nullptr));
+      break;
+    }
+  }
+  if (canon) LQCD_HIP(launch_unpack(g->kg, vout, prec, (double2*)out, nrhs, st));
+  return LQCD_OK;
+}

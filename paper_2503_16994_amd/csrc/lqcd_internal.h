@@ -1,0 +1,93 @@
+// Internal host-side state behind the opaque handles of lqcd.h.
+#pragma once
+
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lqcd.h"
+#include "lqcd_kernels.h"
+
+struct lqcd_geom {
+  lqcd_geom_desc desc;
+  lqcd::KGeom kg;
+  int64_t V;
+  int V2;
+};
+
+struct lqcd_gauge {
+  const lqcd_geom_t* g;
+  int pmask;
+  uint64_t uid;  // distinguishes gauge fields for the clover cache
+  double2* U64;
+  float2* U32;
+  lqcd::bf16x2* U16;
+};
+
+// Device memory map of a workspace (all pointers into the caller's memory).
+struct WsLayout {
+  size_t bytes = 0;
+  // clover: A on both parities [2][2][18][V2], inverse on odd sites [2][18][V2]
+  double2 *C64 = nullptr, *Ci64 = nullptr;
+  float2 *C32 = nullptr, *Ci32 = nullptr;
+  lqcd::bf16x2 *C16 = nullptr, *Ci16 = nullptr;
+  int* err_flag = nullptr;
+  // FP64 full-lattice vectors [nrhs][2][12][V2]
+  double2 *E = nullptr, *X = nullptr, *TMP = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr,
+          *AP = nullptr, *EH = nullptr;
+  // inner-precision half vectors [nrhs][12][V2] (FP32 storage) and BF16 copies
+  float2 *xl = nullptr, *rl = nullptr, *pl = nullptr, *ql = nullptr, *apl = nullptr, *tl = nullptr;
+  lqcd::bf16x2 *pb = nullptr, *qb = nullptr, *tb = nullptr;
+  // reductions
+  double* partials = nullptr;  // [nrhs][max_parts]
+  double* partials2 = nullptr; // [nrhs][max_parts]
+  int max_parts = 0;
+  lqcd::CGState* cg = nullptr; // [nrhs]
+  double* scal = nullptr;      // [4][nrhs]
+};
+
+struct lqcd_ws {
+  const lqcd_geom_t* g;
+  int pmask;
+  int nrhs;
+  WsLayout m;
+  // clover cache key
+  bool clover_valid = false;
+  uint64_t clover_uid = 0;
+  double kappa = 0, csw = 0, cF = 0;
+  int clover_pmask = 0;
+};
+
+namespace lqcd {
+
+void set_error(const char* fmt, ...);
+int fail(int status, const char* fmt, ...);
+WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base);
+int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipStream_t st);
+int check_dirac(const lqcd_dirac* d);
+
+inline int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LQCD_OK;
+  return fail(LQCD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LQCD_HIP(call)                                        \
+  do {                                                        \
+    hipError_t _e = (call);                                   \
+    if (_e != hipSuccess) return ::lqcd::hip_status(_e, #call); \
+  } while (0)
+
+// Description of one hop launch over a full-layout vector: parity p_out of
+// `out` from parity 1-p_out of `y` (and p_out of `z`).
+struct HopSpec {
+  int prec;  // links/clover precision
+  int in_prec, out_prec;
+  int pre, post;
+  bool hop = true;
+  bool g5 = false;
+  double scale = 0.0;
+};
+
+}  // namespace lqcd

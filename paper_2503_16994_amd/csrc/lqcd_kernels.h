@@ -1,0 +1,164 @@
+// Host-side launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lqcd_dev.h"
+
+namespace lqcd {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+inline size_t elem_bytes(int prec) { return prec == P_F64 ? 16 : (prec == P_F32 ? 8 : 4); }
+
+// Self-term of a hop launch
+enum PreMode { PRE_NONE = 0, PRE_IDENT = 1, PRE_CLOV = 2 };
+// Matrix applied to the whole result
+enum PostMode { POST_NONE = 0, POST_CLOV = 1 };
+
+// One launch of the hopping kernel:
+//   out = post( pre(z) + scale * H y ),  H = sum_mu [(1-g)U y(x+mu) + (1+g)U^+ y(x-mu)]
+// on the sites of parity p_out, then optionally g5, the SF output mask and
+// per-block |out|^2 partial sums.  All vector pointers point at the first
+// rhs of the relevant parity; *_rs are element strides between rhs.
+struct HopLaunch {
+  KGeom g;
+  int prec;       // storage precision of links/clover (P_*)
+  int in_prec;    // storage precision of y, z
+  int out_prec;   // storage precision of out
+  int p_out;
+  const void* U;     // links (both parities), precision prec
+  const void* y;     // opposite-parity input
+  const void* z;     // same-parity input (PRE_IDENT / PRE_CLOV)
+  const void* Cpre;  // clover blocks of parity p_out (2 x 18 x V2)
+  const void* Cpost; // clover inverse blocks of parity p_out
+  void* out;
+  long y_rs, z_rs, out_rs;
+  int nrhs;
+  int pre, post;
+  bool g5;
+  bool hop;          // false: no hopping term (pure block application)
+  double scale;
+  double* partials;  // [nrhs][nblocks] or nullptr
+  const int* done;   // early-exit flag (device) or nullptr
+  int nr_tile;       // rhs per thread (1, 2, 3, 4)
+  // both = true: one launch covers both parities (first half of the grid
+  // parity 0, second half parity 1); y, z, out then point at the parity-0
+  // part of full vectors, parity 1 lies par_stride elements further and the
+  // Cpre blocks of parity 1 cpre_par elements further.
+  bool both;
+  long par_stride;
+  long cpre_par;
+};
+
+int hop_nblocks(const HopLaunch& h);
+hipError_t launch_hop(const HopLaunch& h, hipStream_t st);
+
+// Gauge import: canonical complex128 U -> internal links (any non-null
+// precision pointer is written); OPEN zeroes U_t(T-1).
+hipError_t launch_import_gauge(const KGeom& g, const double2* Ucanon, double2* U64, float2* U32,
+                               bf16x2* U16, hipStream_t st);
+
+// Spinor layout conversion.  Internal "full" vector: [rhs][parity][k][s].
+// pack: canonical [rhs][site][12] -> internal (g5 optional), precision prec.
+hipError_t launch_pack(const KGeom& g, const double2* canon, void* internal, int prec, int nrhs,
+                       bool g5, hipStream_t st);
+hipError_t launch_unpack(const KGeom& g, const void* internal, int prec, double2* canon,
+                         int nrhs, hipStream_t st);
+
+// Clover: builds A on both parities (FP64 + optional lower precisions) and the
+// inverse on the odd sites.  err_flag gets bit 1 for a singular block.
+struct CloverLaunch {
+  KGeom g;
+  const double2* U64;
+  double m0, csw, cF;
+  double2* C64;     // [2][2][18][V2]
+  double2* Ci64;    // [2][18][V2] odd inverse
+  float2* C32;
+  float2* Ci32;
+  bf16x2* C16;
+  bf16x2* Ci16;
+  int* err_flag;
+};
+hipError_t launch_clover(const CloverLaunch& c, hipStream_t st);
+
+// ---- vector algebra on flat arrays of n complex elements per rhs -----------
+enum CGStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_NONFINITE = 3 };
+
+// CG control of one right-hand side (device memory)
+struct CGState {
+  double rr;       // |r|^2 of the recursion
+  double rr_prev;
+  double rr_max;   // max |r|^2 since the last reliable update
+  double pAp;      // |Dhat p|^2
+  double alpha, beta;
+  double bnorm2;   // |b|^2, b the normal-equation right-hand side
+  double eta2;     // |eta|^2
+  double tol2;     // converged when |eta - Dw x|^2 <= tol2
+  double target2;  // inner target on |r|^2 (reliable update when reached)
+  double delta2;   // reliable update when |r|^2 < delta2 * rr_max (0: never)
+  double rho2;     // last true residual |eta - Dw x|^2 / |eta|^2
+  int done;        // 1: no further updates
+  int skip_ru;     // 0: a reliable update is pending
+  int status;      // CGStatus
+  int iters;
+  int maxiter;
+  int rupd;        // reliable updates performed
+  int restarts;    // inner target tightenings
+  int inner_hit;
+  int ru_every;    // reliable update at least every ru_every iterations (0: off)
+  int last_ru;     // iteration of the last reliable update
+};
+
+struct CGSetup {
+  int nrhs;
+  int maxiter;
+  double tol;        // true relative residual target
+  double inner_rel;  // initial inner target relative to |b|
+  double delta2;
+  int ru_every;
+};
+
+int blas_nblocks(long n);
+hipError_t launch_norm2(const void* x, int prec, long n, long rs, int nrhs, double* partials,
+                        hipStream_t st);
+// sum partials (fixed order) into dst[r] (FP64)
+hipError_t launch_reduce(const double* partials, int nparts, int nrhs, double* dst,
+                         hipStream_t st);
+hipError_t launch_cg_setup(CGState* s, const double* b2, const double* eta2, const CGSetup& cfg,
+                           hipStream_t st);
+hipError_t launch_cg_alpha(CGState* s, const double* partials, int nparts, int nrhs,
+                           hipStream_t st);
+hipError_t launch_cg_beta(CGState* s, const double* partials, int nparts, int nrhs,
+                          hipStream_t st);
+hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, const void* Ap,
+                        int prec, long n, long rs, int nrhs, const CGState* s, double* partials,
+                        hipStream_t st);
+hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs,
+                       const CGState* s, void* p_lo, int lo_prec, hipStream_t st);
+// reliable-update kernels (each skips rhs without a pending update)
+hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs,
+                          const CGState* s, hipStream_t st);
+hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs,
+                         long V2, int nrhs, const CGState* s, double* partials, hipStream_t st);
+hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
+                          const CGState* s, hipStream_t st);
+hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r,
+                            int n_r, int nrhs, hipStream_t st);
+
+// y = a*x + b*y  (element types by precision), per-rhs scalars not needed
+hipError_t launch_axpby(double a, const void* x, int xprec, double b, void* y, int yprec,
+                        long n, long rs_x, long rs_y, int nrhs, hipStream_t st);
+// y = x converted between precisions
+hipError_t launch_convert(const void* x, int xprec, void* y, int yprec, long n, long rs_x,
+                          long rs_y, int nrhs, hipStream_t st);
+// out = x - y (FP64) with partial |out|^2
+hipError_t launch_sub_norm(const double2* x, const double2* y, double2* out, long n, long rs,
+                           int nrhs, double* partials, hipStream_t st);
+hipError_t launch_fill_zero(void* x, size_t bytes, hipStream_t st);
+// x (even half vector) *= g5 in place
+hipError_t launch_g5(void* x, int prec, long V2, long rs, int nrhs, hipStream_t st);
+
+}  // namespace lqcd

@@ -1,0 +1,443 @@
+// lqcd_solve: conjugate gradient on the normal equations (paper Sec. 3.3,
+// CG!/propagator!), on the full lattice or even-odd preconditioned, with an
+// optional reduced-precision inner iteration and FP64 reliable updates.
+//
+// Even-odd form.  With A the site-diagonal clover term and H the hopping
+// sum, Dw = [[A_ee, D_eo], [D_oe, A_oo]], D = -H/2, and the Schur complement
+//   Dhat = A_ee - D_eo A_oo^{-1} D_oe
+// acts on even sites.  The solve is
+//   eta_hat = eta_e - D_eo A_oo^{-1} eta_o,   CG on Dhat^+ Dhat x = Dhat^+ eta_hat,
+//   psi_e = x,  psi_o = A_oo^{-1} (eta_o - D_oe psi_e),
+// and Dhat^+ = g5 Dhat g5.  One CG iteration is four hop launches (the g5 and
+// |Dhat p|^2 fused into the second), one alpha, the fused x/r update with
+// |r|^2, one beta and the p update.  All CG scalars stay on the device; the
+// host reads them once per chunk of iterations.
+//
+// Stopping and reliable updates.  The target is the true relative residual
+// |eta - Dw psi|/|eta| <= tol.  The recursion runs in the inner precision.
+// A reliable update recomputes the residual in FP64 from the FP64 solution
+// (Sleijpen and van der Vorst's reliable updates, as used for mixed-precision
+// lattice solvers by Clark et al.): s = eta_hat - Dhat x, whose norm equals
+// the full-lattice residual because the odd rows are solved exactly, then
+// r = Dhat^+ s with the search direction p kept.  It is requested by the beta
+// kernel when |r| has dropped by delta = 0.1 since the last update (mixed
+// precision only) or reaches the inner target (tol/10)|b|; the update kernels
+// sit after every fifth iteration and skip rhs without a request.  The
+// update's last kernel declares an rhs converged when |s|/|eta| <= tol, and
+// otherwise tightens the inner target tenfold if it had been reached.  All
+// control stays on the device: the host polls the done flags once per chunk
+// of iterations, and a chunk can be captured in a hipGraph and replayed.  At
+// the end psi is reconstructed and |eta - Dw psi| is recomputed with the FP64
+// full-lattice operator.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
+#include "lqcd_internal.h"
+
+using namespace lqcd;
+
+namespace {
+
+struct Ctl {
+  hipStream_t st;
+  const lqcd_geom_t* g;
+  const lqcd_gauge* u;
+  lqcd_ws* w;
+  int nrhs;
+};
+
+const void* links_of(const lqcd_gauge* u, int prec) {
+  return prec == P_F64 ? (const void*)u->U64 : (prec == P_F32 ? (const void*)u->U32 : (const void*)u->U16);
+}
+const void* clov_of(const lqcd_ws* w, int prec) {
+  return prec == P_F64 ? (const void*)w->m.C64 : (prec == P_F32 ? (const void*)w->m.C32 : (const void*)w->m.C16);
+}
+const void* cloi_of(const lqcd_ws* w, int prec) {
+  return prec == P_F64 ? (const void*)w->m.Ci64 : (prec == P_F32 ? (const void*)w->m.Ci32 : (const void*)w->m.Ci16);
+}
+
+// a vector operand: base pointer of rhs 0 at the relevant parity, its
+// storage precision and its rhs stride (elements)
+struct Vec {
+  void* p;
+  int prec;
+  long rs;
+};
+
+Vec odd_part(const Vec& v, long V2) {
+  return Vec{(char*)v.p + (size_t)12 * V2 * elem_bytes(v.prec), v.prec, v.rs};
+}
+
+HopLaunch mk(const Ctl& c, int lprec) {
+  HopLaunch h;
+  memset(&h, 0, sizeof(h));
+  h.g = c.g->kg;
+  h.prec = lprec;
+  h.U = links_of(c.u, lprec);
+  h.nrhs = c.nrhs;
+  h.nr_tile = 1;
+  h.hop = true;
+  return h;
+}
+
+// out_o = A_oo^{-1} D_oe y_e = A_oo^{-1} (-1/2 H y_e)
+hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, int nr_tile) {
+  HopLaunch h = mk(c, lprec);
+  h.p_out = 1;
+  h.in_prec = y.prec;
+  h.out_prec = out_o.prec;
+  h.y = y.p;
+  h.y_rs = y.rs;
+  h.out = out_o.p;
+  h.out_rs = out_o.rs;
+  h.Cpost = cloi_of(c.w, lprec);
+  h.pre = PRE_NONE;
+  h.post = POST_CLOV;
+  h.scale = -0.5;
+  h.done = done;
+  h.nr_tile = nr_tile;
+  return launch_hop(h, c.st);
+}
+
+// out_e = [g5] (A_ee z_e + 1/2 H t_o), optional |out|^2 partials
+hipError_t hop_oe(const Ctl& c, int lprec, Vec z, Vec t_o, Vec out, bool g5, double* partials,
+                  const int* done, int nr_tile) {
+  HopLaunch h = mk(c, lprec);
+  h.p_out = 0;
+  h.in_prec = z.prec;
+  h.out_prec = out.prec;
+  h.y = t_o.p;
+  h.y_rs = t_o.rs;
+  h.z = z.p;
+  h.z_rs = z.rs;
+  h.out = out.p;
+  h.out_rs = out.rs;
+  h.Cpre = clov_of(c.w, lprec);
+  h.pre = PRE_CLOV;
+  h.post = POST_NONE;
+  h.scale = 0.5;
+  h.g5 = g5;
+  h.partials = partials;
+  h.done = done;
+  h.nr_tile = nr_tile;
+  return launch_hop(h, c.st);
+}
+
+// out (full, both parities) = [g5] Dw y, optional partials
+hipError_t dw_full(const Ctl& c, const double2* y, double2* out, bool g5, double* partials,
+                   const int* done) {
+  HopLaunch h = mk(c, P_F64);
+  const long V2 = c.g->V2;
+  h.in_prec = h.out_prec = P_F64;
+  h.both = true;
+  h.par_stride = 12 * V2;
+  h.cpre_par = 36 * V2;
+  h.y = y;
+  h.z = y;
+  h.out = out;
+  h.y_rs = h.z_rs = h.out_rs = 24 * V2;
+  h.Cpre = c.w->m.C64;
+  h.pre = PRE_CLOV;
+  h.post = POST_NONE;
+  h.scale = -0.5;
+  h.g5 = g5;
+  h.partials = partials;
+  h.done = done;
+  return launch_hop(h, c.st);
+}
+
+// out_e = z_e + 1/2 H y_o   (eta_hat from eta_e and A_oo^{-1} eta_o)
+hipError_t hop_oe_ident(const Ctl& c, Vec z, Vec y_o, Vec out) {
+  HopLaunch h = mk(c, P_F64);
+  h.p_out = 0;
+  h.in_prec = h.out_prec = P_F64;
+  h.y = y_o.p;
+  h.y_rs = y_o.rs;
+  h.z = z.p;
+  h.z_rs = z.rs;
+  h.out = out.p;
+  h.out_rs = out.rs;
+  h.pre = PRE_IDENT;
+  h.post = POST_NONE;
+  h.scale = 0.5;
+  return launch_hop(h, c.st);
+}
+
+// out_o = A_oo^{-1} (z_o + s H y_e)  (hop = false: A_oo^{-1} z_o)
+hipError_t clover_inv_apply(const Ctl& c, Vec z_o, Vec y_e, Vec out_o, bool hop, double s) {
+  HopLaunch h = mk(c, P_F64);
+  h.p_out = 1;
+  h.in_prec = h.out_prec = P_F64;
+  h.y = y_e.p;
+  h.y_rs = y_e.rs;
+  h.z = z_o.p;
+  h.z_rs = z_o.rs;
+  h.out = out_o.p;
+  h.out_rs = out_o.rs;
+  h.Cpost = c.w->m.Ci64;
+  h.pre = PRE_IDENT;
+  h.post = POST_CLOV;
+  h.hop = hop;
+  h.scale = s;
+  return launch_hop(h, c.st);
+}
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~GraphCache() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
+
+}  // namespace
+
+extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, const void* eta, void* psi,
+                          lqcd_ws_t* w, void* stream, lqcd_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!u || !prm || !eta || !psi || !w || !info) return fail(LQCD_EINVAL, "lqcd_solve: null pointer");
+  int rc = check_dirac(&prm->d);
+  if (rc) return rc;
+  const int N = prm->nrhs;
+  if (N < 1 || N > w->nrhs) return fail(LQCD_EINVAL, "lqcd_solve: nrhs=%d (workspace holds %d)", N, w->nrhs);
+  if (prm->solver != LQCD_SOLVER_CG_FULL && prm->solver != LQCD_SOLVER_CG_EO)
+    return fail(LQCD_EINVAL, "lqcd_solve: unknown solver %d", prm->solver);
+  const int ip = prm->inner_prec;
+  if (ip < LQCD_F64 || ip > LQCD_BF16) return fail(LQCD_EINVAL, "lqcd_solve: bad inner precision %d", ip);
+  if (prm->solver == LQCD_SOLVER_CG_FULL && ip != LQCD_F64)
+    return fail(LQCD_EINVAL, "lqcd_solve: the full-lattice solver runs in FP64 only");
+  if (!((1 << ip) & u->pmask) || !((1 << ip) & w->pmask))
+    return fail(LQCD_EINVAL, "lqcd_solve: inner precision %d not held by gauge field and workspace", ip);
+  if (!(prm->tol > 0.0) || !(prm->tol < 1.0)) return fail(LQCD_EINVAL, "lqcd_solve: tol must be in (0,1)");
+  if (prm->maxiter < 1) return fail(LQCD_EINVAL, "lqcd_solve: maxiter must be >= 1");
+  if (eta == psi) return fail(LQCD_EINVAL, "lqcd_solve: eta and psi must differ");
+
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_clover(u, &prm->d, w, st);
+  if (rc) return rc;
+
+  const lqcd_geom_t* g = w->g;
+  const long V2 = g->V2;
+  const WsLayout& m = w->m;
+  Ctl c{st, g, u, w, N};
+  const long FRS = 24 * V2, HRS = 12 * V2;
+  const bool eo = (prm->solver == LQCD_SOLVER_CG_EO);
+  const bool mixed = eo && ip != LQCD_F64;
+  const double tol = prm->tol;
+
+  // ---- validate the source: finite, and zero on the SF Dirichlet slice ----
+  double* parts = m.partials;
+  double* parts2 = m.partials2;
+  double* scal = m.scal;  // [0,N) |b|^2  [N,2N) |eta|^2  [2N,3N) |eta(t=0)|^2  [3N,4N) final
+  std::vector<double> h_eta2(N);
+  {
+    const long nsite = g->V * 12;
+    LQCD_HIP(launch_norm2(eta, P_F64, nsite, nsite, N, parts, st));
+    LQCD_HIP(launch_reduce(parts, blas_nblocks(nsite), N, scal + N, st));
+    const bool sf = g->desc.bc == LQCD_BC_SF;
+    if (sf) {
+      const long nslice = g->V / g->desc.L[3] * 12;  // t = 0 is the first slice
+      LQCD_HIP(launch_norm2(eta, P_F64, nslice, nsite, N, parts, st));
+      LQCD_HIP(launch_reduce(parts, blas_nblocks(nslice), N, scal + 2 * N, st));
+    }
+    std::vector<double> tmp(2 * N, 0.0);
+    LQCD_HIP(hipMemcpyAsync(tmp.data(), scal + N, sizeof(double) * (sf ? 2 * N : N),
+                            hipMemcpyDeviceToHost, st));
+    LQCD_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < N; ++r) {
+      h_eta2[r] = tmp[r];
+      if (!isfinite(tmp[r])) return fail(LQCD_ENUMERIC, "lqcd_solve: source %d has NaN/Inf entries", r);
+      if (sf && tmp[N + r] != 0.0)
+        return fail(LQCD_EINVAL, "lqcd_solve: source %d is non-zero on the SF boundary slice t=0", r);
+    }
+  }
+
+  // ---- operands -------------------------------------------------------------
+  const Vec E{m.E, P_F64, FRS}, X{m.X, P_F64, FRS}, TMP{m.TMP, P_F64, FRS}, R{m.R, P_F64, FRS},
+      P{m.P, P_F64, FRS}, Q{m.Q, P_F64, FRS}, AP{m.AP, P_F64, FRS}, EH{m.EH, P_F64, FRS};
+  const size_t full_bytes = (size_t)N * FRS * 16;
+  CGState* cg = m.cg;
+  const int* done = &cg[0].done;
+  const int* skip_ru = &cg[0].skip_ru;
+  const int nb_hop = (int)((V2 + 255) / 256);
+
+  LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
+  LQCD_HIP(launch_fill_zero(m.X, full_bytes, st));
+
+  // b = Dhat^+ eta_hat (eo) or Dw^+ eta (full) into R, with |b|^2
+  int nb_op;  // partial count of the norm-producing operator launch
+  if (eo) {
+    LQCD_HIP(launch_fill_zero(m.EH, full_bytes, st));
+    LQCD_HIP(launch_fill_zero(m.TMP, full_bytes, st));
+    LQCD_HIP(clover_inv_apply(c, odd_part(E, V2), E, odd_part(TMP, V2), false, 0.0));  // A_oo^-1 eta_o
+    LQCD_HIP(hop_oe_ident(c, E, odd_part(TMP, V2), EH));                               // eta_hat
+    LQCD_HIP(hipMemcpyAsync(m.AP, m.EH, full_bytes, hipMemcpyDeviceToDevice, st));
+    LQCD_HIP(launch_g5(m.AP, P_F64, V2, FRS, N, st));
+    LQCD_HIP(hop_eo(c, P_F64, AP, odd_part(TMP, V2), nullptr, 1));
+    LQCD_HIP(hop_oe(c, P_F64, AP, odd_part(TMP, V2), R, true, parts, nullptr, 1));
+    nb_op = nb_hop;
+  } else {
+    LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.Q, P_F64, N, true, st));  // g5 eta
+    LQCD_HIP(dw_full(c, m.Q, m.R, true, parts, nullptr));
+    nb_op = 2 * nb_hop;
+  }
+  LQCD_HIP(launch_reduce(parts, nb_op, N, scal, st));
+
+  // inner operands
+  const bool lo16 = (ip == LQCD_BF16);  // BF16 storage of the operator's operands
+  Vec xi, ri, pi, qi, api, ti, pin, qin, tin;
+  long n_vec;  // complex elements per rhs of one inner vector
+  if (!mixed) {
+    xi = X; ri = R; pi = P; qi = Q; api = AP; ti = odd_part(TMP, V2);
+    pin = pi; qin = qi; tin = ti;
+    n_vec = eo ? 12 * V2 : 24 * V2;
+    LQCD_HIP(hipMemcpyAsync(m.P, m.R, full_bytes, hipMemcpyDeviceToDevice, st));
+  } else {
+    xi = Vec{m.xl, P_F32, HRS}; ri = Vec{m.rl, P_F32, HRS}; pi = Vec{m.pl, P_F32, HRS};
+    qi = Vec{m.ql, P_F32, HRS}; api = Vec{m.apl, P_F32, HRS}; ti = Vec{m.tl, P_F32, HRS};
+    n_vec = 12 * V2;
+    if (lo16) {
+      pin = Vec{m.pb, P_BF16, HRS}; qin = Vec{m.qb, P_BF16, HRS}; tin = Vec{m.tb, P_BF16, HRS};
+    } else {
+      pin = pi; qin = qi; tin = ti;
+    }
+    LQCD_HIP(launch_fill_zero(m.xl, (size_t)N * HRS * 8, st));
+    LQCD_HIP(launch_convert(m.R, P_F64, m.rl, P_F32, n_vec, FRS, HRS, N, st));
+    LQCD_HIP(launch_convert(m.rl, P_F32, m.pl, P_F32, n_vec, HRS, HRS, N, st));
+    if (lo16) LQCD_HIP(launch_convert(m.rl, P_F32, m.pb, P_BF16, n_vec, HRS, HRS, N, st));
+  }
+  const int lprec = mixed ? ip : P_F64;
+  const int nb_blas = blas_nblocks(n_vec);
+  const int nr_tile = 1;
+
+  CGSetup cfg;
+  cfg.nrhs = N;
+  cfg.maxiter = prm->maxiter;
+  cfg.tol = tol;
+  cfg.inner_rel = 0.1 * tol;
+  cfg.delta2 = mixed ? 0.01 : 0.0;
+  cfg.ru_every = mixed ? (prm->reliable_every > 0 ? prm->reliable_every : 100) : 0;
+  LQCD_HIP(launch_cg_setup(cg, scal, scal + N, cfg, st));
+
+  // ---- reliable update group (skips rhs without a pending request) ---------
+  auto reliable_update = [&]() -> hipError_t {
+    hipError_t e;
+    if (eo) {
+      if (mixed && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
+      if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, 1))) return e;
+      if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, 1))) return e;
+      if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, V2, N, cg, parts2, st))) return e;
+      if ((e = hop_eo(c, P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
+      if ((e = hop_oe(c, P_F64, AP, odd_part(TMP, V2), mixed ? Q : R, true, parts, skip_ru, 1))) return e;
+      if (mixed && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
+      return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_hop, N, st);
+    }
+    if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
+    if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, V2, N, cg, parts2, st))) return e;
+    if ((e = dw_full(c, m.AP, m.R, true, parts, skip_ru))) return e;
+    return launch_ru_finish(cg, parts2, blas_nblocks(24 * V2), parts, 2 * nb_hop, N, st);
+  };
+
+  // ---- one CG iteration (graph-capturable: kernels only) --------------------
+  constexpr int kRuStride = 5;
+  auto iteration = [&](int i) -> hipError_t {
+    hipError_t e;
+    if (eo) {
+      if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
+      if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
+    } else {
+      if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
+    }
+    if ((e = launch_cg_alpha(cg, parts, nb_op, N, st))) return e;
+    if (eo) {
+      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile))) return e;
+      if ((e = hop_oe(c, lprec, qin, tin, api, true, nullptr, done, nr_tile))) return e;
+    } else {
+      if ((e = dw_full(c, (const double2*)qin.p, (double2*)api.p, true, nullptr, done))) return e;
+    }
+    if ((e = launch_cg_xr(xi.p, xi.prec, xi.rs, ri.p, pi.p, api.p, ri.prec, n_vec, ri.rs, N, cg, parts, st)))
+      return e;
+    if ((e = launch_cg_beta(cg, parts, nb_blas, N, st))) return e;
+    if ((i + 1) % kRuStride == 0 && (e = reliable_update())) return e;
+    if ((e = launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, lo16 ? pin.p : nullptr,
+                         lo16 ? P_BF16 : P_F32, st)))
+      return e;
+    return hipSuccess;
+  };
+
+  constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
+  GraphCache gc;
+  const bool use_graph = prm->use_graph && st != nullptr;
+  auto run_chunk = [&]() -> int {
+    if (use_graph) {
+      if (!gc.exec) {
+        LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < K && e == hipSuccess; ++i) e = iteration(i);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(st, &gr);
+        if (e != hipSuccess) return hip_status(e, "graph capture");
+        if (e2 != hipSuccess) return hip_status(e2, "hipStreamEndCapture");
+        gc.graph = gr;
+        LQCD_HIP(hipGraphInstantiate(&gc.exec, gr, nullptr, nullptr, 0));
+      }
+      LQCD_HIP(hipGraphLaunch(gc.exec, st));
+      return LQCD_OK;
+    }
+    for (int i = 0; i < K; ++i) LQCD_HIP(iteration(i));
+    return LQCD_OK;
+  };
+
+  std::vector<CGState> hs(N);
+  const bool trace = getenv("LQCD_TRACE") != nullptr;  // per-chunk progress on stderr
+  const long max_chunks = (long)prm->maxiter / K + 3;
+  for (long chunk = 0;; ++chunk) {
+    rc = run_chunk();
+    if (rc) return rc;
+    LQCD_HIP(hipMemcpyAsync(hs.data(), cg, sizeof(CGState) * N, hipMemcpyDeviceToHost, st));
+    LQCD_HIP(hipStreamSynchronize(st));
+    bool all_done = true;
+    for (int r = 0; r < N; ++r) {
+      all_done = all_done && hs[r].done;
+      if (trace)
+        fprintf(stderr, "[lqcd] rhs %d iters %d done %d status %d rr/b2 %.3e rho %.3e rupd %d\n", r,
+                hs[r].iters, hs[r].done, hs[r].status, hs[r].rr / hs[r].bnorm2, sqrt(hs[r].rho2),
+                hs[r].rupd);
+    }
+    if (all_done || chunk >= max_chunks) break;
+  }
+
+  // ---- reconstruct the odd sites, unpack, FP64 full-lattice residual -------
+  if (mixed) LQCD_HIP(launch_axpby(1.0, m.xl, P_F32, 1.0, m.X, P_F64, n_vec, HRS, FRS, N, st));
+  if (eo) LQCD_HIP(clover_inv_apply(c, odd_part(E, V2), X, odd_part(X, V2), true, 0.5));
+  LQCD_HIP(launch_unpack(g->kg, m.X, P_F64, (double2*)psi, N, st));
+  LQCD_HIP(dw_full(c, m.X, m.TMP, false, nullptr, nullptr));
+  LQCD_HIP(launch_sub_norm(m.E, m.TMP, m.AP, 24 * V2, FRS, N, parts, st));
+  LQCD_HIP(launch_reduce(parts, blas_nblocks(24 * V2), N, scal + 3 * N, st));
+  std::vector<double> fres(N);
+  LQCD_HIP(hipMemcpyAsync(fres.data(), scal + 3 * N, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+  LQCD_HIP(hipMemcpyAsync(hs.data(), cg, sizeof(CGState) * N, hipMemcpyDeviceToHost, st));
+  LQCD_HIP(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int overall = LQCD_OK;
+  for (int r = 0; r < N; ++r) {
+    info[r].iters = hs[r].iters;
+    info[r].reliable_updates = hs[r].rupd;
+    info[r].restarts = hs[r].restarts;
+    info[r].true_residual = (h_eta2[r] > 0.0) ? sqrt(fres[r] / h_eta2[r]) : 0.0;
+    info[r].seconds = secs;
+    int stt = LQCD_OK;
+    if (hs[r].status == CG_NONFINITE) stt = LQCD_ENUMERIC;
+    else if (hs[r].status != CG_CONVERGED || !(info[r].true_residual <= tol)) stt = LQCD_ENOCONV;
+    info[r].status = stt;
+    if (stt == LQCD_ENUMERIC) overall = LQCD_ENUMERIC;
+    else if (stt != LQCD_OK && overall == LQCD_OK) overall = LQCD_ENOCONV;
+  }
+  if (overall != LQCD_OK) set_error("lqcd_solve: not every rhs reached tol=%g", tol);
+  return overall;
+}

@@ -1,0 +1,273 @@
+"""Thin Python binding of the C ABI in ``include/lqcd.h``.
+
+Argument marshalling only: every step of the operator and the solve runs in
+the gfx950 kernels of ``liblqcd.so``.  PyTorch provides device memory
+(``torch.empty(..., device="cuda")``) and streams.  There is no fallback: if
+the shared library is missing or cannot be loaded, importing a function
+that needs it raises ``RuntimeError``.
+
+Canonical layouts (complex128, C order): gauge ``U[t, z, y, x, mu, a, b]``,
+spinor ``psi[rhs, t, z, y, x, alpha, a]`` (a single field may omit ``rhs``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblqcd.so")
+
+# status codes
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENUMERIC, ENOTFOUND, EBUSY, EUNSUPPORTED = (
+    0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
+# boundary conditions
+BC_PERIODIC, BC_SF, BC_OPEN = 0, 1, 2
+# precisions and masks
+F64, F32, BF16 = 0, 1, 2
+PM_F64, PM_F32, PM_BF16 = 1, 2, 4
+# operators
+(OP_DW, OP_DW_DAG, OP_G5DW, OP_DWDAGDW, OP_SCHUR, OP_SCHUR_DAG, OP_SCHUR_NORMAL, OP_HOP_EO,
+ OP_HOP_OE) = range(9)
+LAYOUT_CANON, LAYOUT_INTERNAL = 0, 1
+SOLVER_CG_FULL, SOLVER_CG_EO = 0, 1
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lqcd status {status}: {msg}")
+        self.status = status
+
+
+class GeomDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("bc", ctypes.c_int32),
+                ("theta_re", ctypes.c_double * 4), ("theta_im", ctypes.c_double * 4)]
+
+
+class Dirac(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("csw", ctypes.c_double), ("cF", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("d", Dirac), ("solver", ctypes.c_int32), ("inner_prec", ctypes.c_int32),
+                ("reliable_every", ctypes.c_int32), ("maxiter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("nrhs", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("reliable_updates", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# exported symbols and their signatures (restype, argtypes)
+_P, _I, _Z, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+SIGNATURES = {
+    "lqcd_strerror": (ctypes.c_char_p, [_I]),
+    "lqcd_last_error": (ctypes.c_char_p, []),
+    "lqcd_geom": (_I, [ctypes.POINTER(GeomDesc), ctypes.POINTER(_P)]),
+    "lqcd_geom_free": (None, [_P]),
+    "lqcd_geom_volume": (ctypes.c_int64, [_P]),
+    "lqcd_gauge_bytes": (_Z, [_P, _I]),
+    "lqcd_gauge_create": (_I, [_P, _P, _I, _P, _Z, _P, ctypes.POINTER(_P)]),
+    "lqcd_gauge_free": (None, [_P]),
+    "lqcd_ws_bytes": (_Z, [_P, _I, _I]),
+    "lqcd_ws_create": (_I, [_P, _I, _I, _P, _Z, ctypes.POINTER(_P)]),
+    "lqcd_ws_free": (None, [_P]),
+    "lqcd_clover": (_I, [_P, ctypes.POINTER(Dirac), _P, _P]),
+    "lqcd_dw_apply": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _I, _I, _P, _P, _P, _P]),
+    "lqcd_vec_bytes": (_Z, [_P, _I, _I, _I]),
+    "lqcd_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
+}
+
+
+def lib():
+    """Load liblqcd.so (raises if it is not built or cannot be loaded)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2503_16994_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise LqcdError(status, lib().lqcd_last_error().decode())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_bytes(nbytes: int) -> torch.Tensor:
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device="cuda")
+    return t
+
+
+def _aligned_ptr(t: torch.Tensor) -> int:
+    p = t.data_ptr()
+    return (p + 255) & ~255
+
+
+def m0_from_kappa(kappa: float) -> float:
+    return 1.0 / (2.0 * kappa) - 4.0
+
+
+class Lattice:
+    """Geometry handle (lqcd_geom): extents (x, y, z, t), boundary type, theta."""
+
+    def __init__(self, L, bc=BC_PERIODIC, theta=(1, 1, 1, 1)):
+        d = GeomDesc()
+        for i in range(4):
+            d.L[i] = int(L[i])
+            th = complex(theta[i])
+            d.theta_re[i] = th.real
+            d.theta_im[i] = th.imag
+        d.bc = int(bc)
+        h = ctypes.c_void_p()
+        _check(lib().lqcd_geom(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.L = tuple(int(v) for v in L)
+        self.bc = int(bc)
+        self.theta = tuple(complex(t) for t in theta)
+        self.volume = int(lib().lqcd_geom_volume(h))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lqcd_geom_free(self.handle)
+            self.handle = None
+
+    def spinor_shape(self, nrhs=None):
+        Lx, Ly, Lz, T = self.L
+        s = (T, Lz, Ly, Lx, 4, 3)
+        return s if nrhs is None else (nrhs,) + s
+
+
+class GaugeField:
+    """Device-resident gauge field (lqcd_gauge_create) in FP64 and `pmask` precisions."""
+
+    def __init__(self, lat: Lattice, U, pmask=PM_F64, stream=None):
+        self.lat = lat
+        U = torch.as_tensor(U)
+        if U.dtype != torch.complex128:
+            raise TypeError("U must be complex128")
+        U = U.to("cuda").contiguous()
+        nbytes = lib().lqcd_gauge_bytes(lat.handle, pmask)
+        self._mem = _dev_bytes(nbytes)
+        h = ctypes.c_void_p()
+        _check(lib().lqcd_gauge_create(lat.handle, ctypes.c_void_p(U.data_ptr()), pmask,
+                                       ctypes.c_void_p(_aligned_ptr(self._mem)), nbytes,
+                                       _stream_ptr(stream), ctypes.byref(h)))
+        # keep the canonical copy alive until the import kernel has run
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        self.handle = h
+        self.pmask = pmask
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lqcd_gauge_free(self.handle)
+            self.handle = None
+
+
+class Workspace:
+    """Solver/operator workspace (lqcd_ws_create) for up to `nrhs` fields."""
+
+    def __init__(self, lat: Lattice, pmask=PM_F64, nrhs=1):
+        self.lat = lat
+        nbytes = lib().lqcd_ws_bytes(lat.handle, pmask, nrhs)
+        self._mem = _dev_bytes(nbytes)
+        h = ctypes.c_void_p()
+        _check(lib().lqcd_ws_create(lat.handle, pmask, nrhs, ctypes.c_void_p(_aligned_ptr(self._mem)),
+                                    nbytes, ctypes.byref(h)))
+        self.handle = h
+        self.nrhs = nrhs
+        self.pmask = pmask
+        self.nbytes = nbytes
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lqcd_ws_free(self.handle)
+            self.handle = None
+
+
+def dirac(kappa, csw, cF=1.0, mu=0.0) -> Dirac:
+    return Dirac(float(kappa), float(csw), float(cF), float(mu))
+
+
+def clover(gauge: GaugeField, d: Dirac, ws: Workspace, stream=None):
+    _check(lib().lqcd_clover(gauge.handle, ctypes.byref(d), ws.handle, _stream_ptr(stream)))
+
+
+def dw_apply(gauge: GaugeField, d: Dirac, psi: torch.Tensor, op=OP_DW, prec=F64, ws=None,
+             out=None, stream=None) -> torch.Tensor:
+    """Apply an operator to canonical complex128 device field(s)."""
+    lat = gauge.lat
+    single = psi.dim() == 6
+    x = psi.reshape((-1,) + lat.spinor_shape()).contiguous()
+    nrhs = x.shape[0]
+    if ws is None:
+        ws = Workspace(lat, gauge.pmask, nrhs)
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().lqcd_dw_apply(gauge.handle, ctypes.byref(d), op, prec, LAYOUT_CANON, nrhs,
+                               ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               ws.handle, _stream_ptr(stream)))
+    return out[0] if single else out
+
+
+def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torch.Tensor, op, prec,
+                      nrhs, ws: Workspace, stream=None):
+    """Apply an operator to internal-layout vectors (benchmarking)."""
+    _check(lib().lqcd_dw_apply(gauge.handle, ctypes.byref(d), op, prec, LAYOUT_INTERNAL, nrhs,
+                               ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(vout.data_ptr()),
+                               ws.handle, _stream_ptr(stream)))
+
+
+def vec_bytes(lat: Lattice, prec, nrhs, nparity=2) -> int:
+    return int(lib().lqcd_vec_bytes(lat.handle, prec, nrhs, nparity))
+
+
+@dataclass
+class SolveResult:
+    psi: torch.Tensor
+    info: list
+    status: int
+
+
+def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, maxiter=20000,
+          solver=SOLVER_CG_EO, inner_prec=F64, reliable_every=100, use_graph=False, ws=None,
+          stream=None, psi=None, raise_on_noconv=True) -> SolveResult:
+    """Solve Dw psi = eta for canonical complex128 device source(s)."""
+    lat = gauge.lat
+    single = eta.dim() == 6
+    e = eta.reshape((-1,) + lat.spinor_shape()).contiguous()
+    nrhs = e.shape[0]
+    if ws is None:
+        ws = Workspace(lat, gauge.pmask, nrhs)
+    if psi is None:
+        psi = torch.empty_like(e)
+    p = SolveParams(Dirac(float(kappa), float(csw), float(cF), 0.0), solver, inner_prec,
+                    int(reliable_every), int(maxiter), float(tol), nrhs, int(bool(use_graph)))
+    infos = (SolveInfo * nrhs)()
+    st = lib().lqcd_solve(gauge.handle, ctypes.byref(p), ctypes.c_void_p(e.data_ptr()),
+                          ctypes.c_void_p(psi.data_ptr()), ws.handle, _stream_ptr(stream), infos)
+    if st != OK and not (st == ENOCONV and not raise_on_noconv):
+        _check(st)
+    out = psi[0] if single else psi
+    return SolveResult(out, [infos[i].as_dict() for i in range(nrhs)], st)

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI: the shared library loads, exports every
+function ``include/lqcd.h`` declares, and validates arguments before any
+device work.  No GPU is touched: only calls that fail validation (or that
+only compute sizes) are made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lqcd.h")
+
+
+def _lib():
+    from paper_2503_16994_amd import lqcd
+    if not os.path.exists(lqcd.LIB_PATH):
+        from paper_2503_16994_amd import build
+        build.build()
+    return lqcd, lqcd.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lqcd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for required in ("lqcd_geom", "lqcd_dw_apply", "lqcd_solve", "lqcd_clover", "lqcd_gauge_create"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lqcd, L = _lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding binds exactly the declared functions
+    assert set(lqcd.SIGNATURES) >= set(declared_functions()) - {"lqcd_submit", "lqcd_poll"}
+
+
+def _desc(lqcd, L=(4, 4, 4, 8), bc=0, theta=(1, 1, 1, -1)):
+    d = lqcd.GeomDesc()
+    for i in range(4):
+        d.L[i] = L[i]
+        d.theta_re[i] = complex(theta[i]).real
+        d.theta_im[i] = complex(theta[i]).imag
+    d.bc = bc
+    return d
+
+
+@pytest.mark.parametrize("L,bc,theta", [
+    ((4, 4, 4, 7), 0, (1, 1, 1, -1)),      # odd extent
+    ((0, 4, 4, 4), 0, (1, 1, 1, 1)),       # empty extent
+    ((4, 4, 4, 4), 7, (1, 1, 1, 1)),       # unknown boundary type
+    ((4, 4, 4, 4), 0, (1, 1, 1.01, 1)),    # |theta| != 1
+    ((4, 4, 4, 2), 1, (1, 1, 1, 1)),       # SF needs T >= 4
+])
+def test_geometry_validation(L, bc, theta):
+    lqcd, lib = _lib()
+    h = ctypes.c_void_p()
+    st = lib.lqcd_geom(ctypes.byref(_desc(lqcd, L, bc, theta)), ctypes.byref(h))
+    assert st == lqcd.EINVAL
+    assert h.value is None
+    assert len(lib.lqcd_last_error()) > 0
+
+
+def test_geometry_sizes():
+    lqcd, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.lqcd_geom(ctypes.byref(_desc(lqcd, (16, 16, 16, 32))), ctypes.byref(h)) == lqcd.OK
+    V = 16 * 16 * 16 * 32
+    assert lib.lqcd_geom_volume(h) == V
+    # FP64 links: 4 directions x 9 complex x 16 bytes per site
+    assert lib.lqcd_gauge_bytes(h, lqcd.PM_F64) >= V * 4 * 9 * 16
+    assert lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16) >= V * 4 * 9 * 28
+    assert lib.lqcd_vec_bytes(h, lqcd.F64, 12, 2) == 12 * V * 12 * 16
+    assert lib.lqcd_vec_bytes(h, lqcd.BF16, 1, 1) == V // 2 * 12 * 4
+    assert lib.lqcd_ws_bytes(h, lqcd.PM_F64, 12) > lib.lqcd_ws_bytes(h, lqcd.PM_F64, 1)
+    assert lib.lqcd_ws_bytes(h, lqcd.PM_F64, 0) == 0
+    lib.lqcd_geom_free(h)
+
+
+def test_null_and_bad_arguments_are_rejected_without_device_work():
+    lqcd, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.lqcd_geom(None, ctypes.byref(h)) == lqcd.EINVAL
+    assert lib.lqcd_dw_apply(None, None, 0, 0, 0, 1, None, None, None, None) == lqcd.EINVAL
+    assert lib.lqcd_solve(None, None, None, None, None, None, None) == lqcd.EINVAL
+    assert lib.lqcd_gauge_create(None, None, 1, None, 0, None, ctypes.byref(h)) == lqcd.EINVAL
+    assert lib.lqcd_ws_create(None, 1, 1, None, 0, ctypes.byref(h)) == lqcd.EINVAL
+    assert lib.lqcd_strerror(lqcd.ENOCONV) == b"solver did not converge"

@@ -1,0 +1,249 @@
+"""GPU parity: the gfx950 library against the FP64 oracle, through the C ABI.
+
+Tolerances:
+* FP64 operator applications: relative 2-norm difference <= 1e-12 (the two
+  sides sum the same terms in different orders; the observed difference is
+  ~1e-16).
+* FP32 storage/arithmetic: <= 2e-6 relative (a few units of 2^-24 times the
+  ~20 terms per output component).
+* BF16 storage (links, clover, spinors) with FP32 arithmetic: <= 2e-2
+  (several inputs each rounded to 2^-9 relative, plus the rounded output).
+* Solves: the true residual |eta - Dw psi| / |eta| recomputed by the oracle
+  must be <= tol (1e-12 for the 4^4 full-lattice case, 1e-10 otherwise); the
+  error against the oracle's own solution is reported and bounded by
+  cond(Dw) * (rho_gpu + rho_oracle).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2503_16994_amd import inputs, lqcd
+
+pytestmark = pytest.mark.gpu
+
+P, SF, OPEN = 0, 1, 2
+TH_AP = (1, 1, 1, -1)
+TH_RND = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.7])))
+TH_SPATIAL = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.0])))
+
+# (L, bc, theta, eps, kappa, csw, cF); the 6x4x4x6 lattice has V/2 = 288 sites,
+# i.e. one full and one ragged block of 256 threads.
+OP_CASES = [
+    ((4, 4, 4, 4), P, TH_AP, 0.3, 0.12, 1.0, 1.0),
+    ((6, 4, 4, 6), P, TH_RND, 0.3, 0.1345, 1.9, 1.0),
+    ((4, 6, 4, 8), SF, TH_SPATIAL, 0.2, 0.134, 1.8, 1.3),
+    ((4, 4, 6, 6), OPEN, TH_SPATIAL, 0.2, 0.13, 1.9, 0.7),
+    ((8, 6, 4, 10), P, TH_AP, 0.2, 0.135, 1.9, 1.0),
+]
+
+
+def case_id(c):
+    L, bc, *_ = c
+    return f"{'x'.join(map(str, L))}-{['P', 'SF', 'OPEN'][bc]}"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def g5(psi):
+    out = psi.copy()
+    out[..., 2:, :] *= -1
+    return out
+
+
+class Setup:
+    def __init__(self, L, bc, theta, eps, kappa, csw, cF, seed=17, pmask=lqcd.PM_F64):
+        self.L, self.bc, self.theta = L, bc, theta
+        self.kappa, self.csw, self.cF = kappa, csw, cF
+        self.m0 = orc.m0_from_kappa(kappa)
+        self.U = inputs.gauge_field(L, eps, seed=seed, bc=bc)
+        self.A = orc.clover_matrix(L, bc, self.U, self.m0, csw, cF)
+        self.lat = lqcd.Lattice(L, bc, theta)
+        self.gauge = lqcd.GaugeField(self.lat, torch.from_numpy(self.U), pmask)
+        self.d = lqcd.dirac(kappa, csw, cF)
+
+    def fields(self, n, seed=0):
+        return np.stack([inputs.gaussian_spinor(self.L, seed + i, self.bc) for i in range(n)])
+
+    def apply(self, psi, op, prec=lqcd.F64, ws=None):
+        x = torch.from_numpy(np.ascontiguousarray(psi)).cuda()
+        out = lqcd.dw_apply(self.gauge, self.d, x, op=op, prec=prec, ws=ws)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    # oracle side
+    def o_dw(self, psi):
+        return orc.dw(self.L, self.bc, self.theta, self.U, self.A, psi)
+
+    def o_dwdag(self, psi):
+        return orc.dw_dag(self.L, self.bc, self.theta, self.U, self.A, psi)
+
+
+@pytest.fixture(scope="module", params=OP_CASES, ids=case_id)
+def setup(request):
+    print(f"\n[gpu case] {case_id(request.param)}", flush=True)
+    return Setup(*request.param)
+
+
+def test_full_operator_fp64(setup):
+    s = setup
+    psi = s.fields(2, seed=3)
+    ws = lqcd.Workspace(s.lat, lqcd.PM_F64, 2)
+    expect = {
+        lqcd.OP_DW: [s.o_dw(p) for p in psi],
+        lqcd.OP_DW_DAG: [s.o_dwdag(p) for p in psi],
+        lqcd.OP_G5DW: [g5(s.o_dw(p)) for p in psi],
+        lqcd.OP_DWDAGDW: [s.o_dwdag(s.o_dw(p)) for p in psi],
+    }
+    for op, exp in expect.items():
+        got = s.apply(psi, op, ws=ws)
+        for j in range(2):
+            assert rel(got[j], exp[j]) < 1e-12, (op, j, rel(got[j], exp[j]))
+
+
+def test_schur_operators_fp64(setup):
+    s = setup
+    L, bc, th = s.L, s.bc, s.theta
+    Ainv = orc.inverse_blocks(s.A)
+    odd = orc.parity_mask(L)
+    psi = s.fields(1, seed=11)[0]
+    pe = psi.copy()
+    pe[odd] = 0
+    po = psi.copy()
+    po[~odd] = 0
+
+    def dhat(v):
+        return orc.schur_dhat(L, bc, th, s.U, s.A, Ainv, v)
+
+    got = s.apply(psi[None], lqcd.OP_SCHUR)[0]
+    assert rel(got, dhat(pe)) < 1e-12
+    got = s.apply(psi[None], lqcd.OP_SCHUR_DAG)[0]
+    assert rel(got, g5(dhat(g5(pe)))) < 1e-12
+    got = s.apply(psi[None], lqcd.OP_SCHUR_NORMAL)[0]
+    assert rel(got, g5(dhat(g5(dhat(pe))))) < 1e-12
+    got = s.apply(psi[None], lqcd.OP_HOP_EO)[0]
+    assert rel(got, orc.schur_hop_eo(L, bc, th, s.U, Ainv, pe)) < 1e-12
+    # HOP_OE: A_ee x_e - D_eo y_o on the even sites
+    exp = orc.apply_blocks(s.A, pe) - orc.hop(L, bc, th, s.U, po)
+    exp[odd] = 0
+    if bc == SF:
+        exp[0] = 0
+    got = s.apply(psi[None], lqcd.OP_HOP_OE)[0]
+    assert rel(got, exp) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(lqcd.F32, 2e-6), (lqcd.BF16, 2e-2)])
+def test_reduced_precision_operator(prec, tol):
+    c = OP_CASES[1]
+    pm = lqcd.PM_F64 | (lqcd.PM_F32 if prec == lqcd.F32 else lqcd.PM_BF16)
+    s = Setup(*c, pmask=pm)
+    psi = s.fields(1, seed=5)
+    ws = lqcd.Workspace(s.lat, pm, 1)
+    Ainv = orc.inverse_blocks(s.A)
+    odd = orc.parity_mask(s.L)
+    pe = psi[0].copy()
+    pe[odd] = 0
+    dh = orc.schur_dhat(s.L, s.bc, s.theta, s.U, s.A, Ainv, pe)
+    cases = ((lqcd.OP_DW, s.o_dw(psi[0])), (lqcd.OP_DWDAGDW, s.o_dwdag(s.o_dw(psi[0]))),
+             (lqcd.OP_HOP_EO, orc.schur_hop_eo(s.L, s.bc, s.theta, s.U, Ainv, pe)),
+             (lqcd.OP_SCHUR, dh),
+             (lqcd.OP_SCHUR_NORMAL, g5(orc.schur_dhat(s.L, s.bc, s.theta, s.U, s.A, Ainv, g5(dh)))))
+    for op, ref in cases:
+        got = s.apply(psi, op, prec=prec, ws=ws)[0]
+        err = rel(got, ref)
+        print(f"prec {prec} op {op}: rel err {err:.3e}")
+        assert err < tol
+
+
+def _oracle_rho(s, eta, psi):
+    r = eta - s.o_dw(psi)
+    return float(np.linalg.norm(r) / np.linalg.norm(eta))
+
+
+def test_c1_full_cg_4x4x4x4():
+    """Plain FP64 full-lattice CG on Dw^+ Dw, 4^4, point source, 1e-12."""
+    s = Setup((4, 4, 4, 4), P, TH_AP, 0.3, 0.12, 1.0, 1.0, seed=1)
+    eta = inputs.point_source(s.L, (0, 0, 0, 0), 0, 0)
+    res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, tol=1e-12,
+                     solver=lqcd.SOLVER_CG_FULL)
+    psi = res.psi.cpu().numpy()
+    rho = _oracle_rho(s, eta, psi)
+    ref, rho_o, it_o, ok = orc.cg(s.L, P, TH_AP, s.U, s.A, eta, tol=1e-12)
+    print(f"C1: gpu iters {res.info[0]['iters']} rho {rho:.3e}; oracle iters {it_o} rho {rho_o:.3e}; "
+          f"|psi-psi_or|/|psi_or| = {rel(psi, ref):.3e}")
+    assert res.status == lqcd.OK
+    assert rho <= 1e-12 and abs(rho - res.info[0]["true_residual"]) < 1e-14
+    assert rel(psi, ref) < 1e-9
+
+
+@pytest.mark.parametrize("c", OP_CASES[:4], ids=case_id)
+def test_eo_cg_fp64_every_boundary(c):
+    s = Setup(*c, seed=23)
+    x0 = (0, 0, 0, 1) if s.bc == SF else (0, 0, 0, 0)
+    eta = np.stack([inputs.point_source(s.L, x0, 1, 2), inputs.gaussian_spinor(s.L, 9, s.bc)])
+    res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, s.cF, tol=1e-10)
+    psi = res.psi.cpu().numpy()
+    for j in range(2):
+        rho = _oracle_rho(s, eta[j], psi[j])
+        ref, rho_o, _, ok = orc.cg(s.L, s.bc, s.theta, s.U, s.A, eta[j], tol=1e-10)
+        print(f"{case_id(c)} rhs {j}: iters {res.info[j]['iters']} rho {rho:.3e} err {rel(psi[j], ref):.3e}")
+        assert rho <= 1e-10
+        assert rel(psi[j], ref) < 1e-7
+    if s.bc == SF:
+        assert np.all(psi[:, 0] == 0)
+
+
+def test_c2_eo_cg_fp64_16x16x16x32_twelve_sources():
+    """Plain FP64 even-odd CG, 16^3x32, 12 point sources solved one at a time."""
+    s = Setup((16, 16, 16, 32), P, TH_AP, 0.2, 0.1345, 1.9, 1.0, seed=2)
+    ws = lqcd.Workspace(s.lat, lqcd.PM_F64, 1)
+    for j in range(12):
+        eta = inputs.point_source(s.L, (0, 0, 0, 0), j // 3, j % 3)
+        res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, tol=1e-10, ws=ws)
+        psi = res.psi.cpu().numpy()
+        rho = _oracle_rho(s, eta, psi)
+        print(f"C2 source {j}: iters {res.info[0]['iters']} restarts {res.info[0]['restarts']} "
+              f"rho(oracle) {rho:.3e} rho(gpu) {res.info[0]['true_residual']:.3e} "
+              f"t {res.info[0]['seconds']:.3f}s", flush=True)
+        assert res.status == lqcd.OK
+        assert rho <= 1e-10
+
+
+@pytest.mark.parametrize("inner", [lqcd.F32, lqcd.BF16], ids=["f32", "bf16"])
+def test_mixed_precision_eo_cg(inner):
+    pm = lqcd.PM_F64 | (lqcd.PM_F32 if inner == lqcd.F32 else lqcd.PM_BF16)
+    s = Setup((8, 8, 8, 16), P, TH_AP, 0.2, 0.135, 1.9, 1.0, seed=3, pmask=pm)
+    eta = inputs.z2_noise(s.L, seed=3)
+    res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, tol=1e-10,
+                     inner_prec=inner, reliable_every=100, maxiter=20000)
+    psi = res.psi.cpu().numpy()
+    rho = _oracle_rho(s, eta, psi)
+    ref, rho_o, it_o, _ = orc.cg(s.L, P, TH_AP, s.U, s.A, eta, tol=1e-10)
+    print(f"mixed {inner}: iters {res.info[0]['iters']} reliable updates {res.info[0]['reliable_updates']} "
+          f"rho {rho:.3e} err vs oracle {rel(psi, ref):.3e} (oracle iters {it_o})")
+    assert res.status == lqcd.OK
+    assert rho <= 1e-10
+
+
+def test_multi_rhs_equals_single_rhs_bitwise():
+    s = Setup((8, 8, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=4)
+    eta = inputs.point_sources_12(s.L, (0, 0, 0, 0))[:6] + 0.1 * np.stack(
+        [inputs.gaussian_spinor(s.L, k) for k in range(6)])
+    e = torch.from_numpy(eta).cuda()
+    batch = lqcd.solve(s.gauge, e, s.kappa, s.csw, tol=1e-10).psi.cpu().numpy()
+    for j in range(6):
+        alone = lqcd.solve(s.gauge, e[j:j + 1], s.kappa, s.csw, tol=1e-10).psi.cpu().numpy()[0]
+        assert np.array_equal(alone, batch[j]), j
+
+
+def test_graph_capture_matches_eager_and_is_deterministic():
+    s = Setup((8, 8, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=6)
+    eta = torch.from_numpy(inputs.z2_noise(s.L, 1)[None]).cuda()
+    stream = torch.cuda.Stream()
+    eager = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, stream=stream).psi.cpu().numpy()
+    for _ in range(3):
+        g = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.psi.cpu().numpy(), eager)
