@@ -164,6 +164,9 @@ enum { LQCD_LAYOUT_CANON = 0, LQCD_LAYOUT_INTERNAL = 1 };
  * `out` are internal-layout vectors of precision `prec` (size from
  * lqcd_vec_bytes).  `in` and `out` must not overlap.  The clover term is
  * (re)built in `w` when (u, d) differs from the cached one. */
+/* With LQCD_LAYOUT_INTERNAL each operator is exactly its kernel launches
+ * (HOP_EO and HOP_OE are one launch each, SCHUR two): the parity an operator
+ * does not produce is left unchanged in `out`. */
 int lqcd_dw_apply(const lqcd_gauge_t *u, const lqcd_dirac *d, int op, int prec, int layout,
                   int nrhs, const void *in, void *out, lqcd_ws_t *w, void *stream);
 

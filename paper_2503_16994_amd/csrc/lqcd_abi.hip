@@ -248,7 +248,14 @@ extern "C" int lqcd_ws_create(const lqcd_geom_t* g, int pmask, int nrhs, void* m
   return LQCD_OK;
 }
 
-extern "C" void lqcd_ws_free(lqcd_ws_t* w) { delete w; }
+extern "C" void lqcd_ws_free(lqcd_ws_t* w) {
+  if (!w) return;
+  for (auto& e : w->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  delete w;
+}
 
 extern "C" size_t lqcd_vec_bytes(const lqcd_geom_t* g, int prec, int nrhs, int nparity) {
   if (!g || nrhs < 1 || nparity < 1 || nparity > 2 || prec < 0 || prec > 2) return 0;
@@ -468,24 +475,23 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
         LQCD_HIP(launch_g5(tmp2, prec, g->V2, 12L * g->V2, 2 * nrhs, st));
         vin = tmp2;
       }
-      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
       LQCD_HIP(apply_hop_eo(c, vin, tmp));
       LQCD_HIP(apply_hop_oe(c, vin, tmp, vout, op == LQCD_OP_SCHUR_DAG, nullptr));
       break;
     case LQCD_OP_SCHUR_NORMAL:
-      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
-      LQCD_HIP(launch_fill_zero(tmp2, full_bytes, st));
+      if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
       LQCD_HIP(apply_hop_eo(c, vin, tmp));
       LQCD_HIP(apply_hop_oe(c, vin, tmp, tmp2, true, nullptr));
       LQCD_HIP(apply_hop_eo(c, tmp2, tmp));
       LQCD_HIP(apply_hop_oe(c, tmp2, tmp, vout, true, nullptr));
       break;
     case LQCD_OP_HOP_EO:
-      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
       LQCD_HIP(apply_hop_eo(c, vin, vout));
       break;
     case LQCD_OP_HOP_OE: {
-      LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
+      if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
       LQCD_HIP(apply_hop_oe(c, vin, vin, vout, false, nullptr));
       break;
     }

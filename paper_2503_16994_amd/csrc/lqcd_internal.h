@@ -48,6 +48,15 @@ struct WsLayout {
   double* scal = nullptr;      // [4][nrhs]
 };
 
+// A captured chunk of solver iterations, valid for the workspace's lifetime
+// (its kernels read and write only the gauge field and workspace memory).
+struct GraphEntry {
+  uint64_t gauge_uid;
+  int solver, inner_prec, nrhs, chunk;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 struct lqcd_ws {
   const lqcd_geom_t* g;
   int pmask;
@@ -58,6 +67,7 @@ struct lqcd_ws {
   uint64_t clover_uid = 0;
   double kappa = 0, csw = 0, cF = 0;
   int clover_pmask = 0;
+  std::vector<GraphEntry> graphs;
 };
 
 namespace lqcd {

@@ -186,15 +186,6 @@ hipError_t clover_inv_apply(const Ctl& c, Vec z_o, Vec y_e, Vec out_o, bool hop,
   return launch_hop(h, c.st);
 }
 
-struct GraphCache {
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  ~GraphCache() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-  }
-};
-
 }  // namespace
 
 extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, const void* eta, void* psi,
@@ -371,22 +362,35 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   };
 
   constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
-  GraphCache gc;
   const bool use_graph = prm->use_graph && st != nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    for (auto& e : w->graphs)
+      if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == ip && e.nrhs == N &&
+          e.chunk == K)
+        exec = e.exec;
+  }
   auto run_chunk = [&]() -> int {
     if (use_graph) {
-      if (!gc.exec) {
+      if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int i = 0; i < K && e == hipSuccess; ++i) e = iteration(i);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(st, &gr);
-        if (e != hipSuccess) return hip_status(e, "graph capture");
+        if (e != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return hip_status(e, "graph capture");
+        }
         if (e2 != hipSuccess) return hip_status(e2, "hipStreamEndCapture");
-        gc.graph = gr;
-        LQCD_HIP(hipGraphInstantiate(&gc.exec, gr, nullptr, nullptr, 0));
+        hipError_t e3 = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) {
+          (void)hipGraphDestroy(gr);
+          return hip_status(e3, "hipGraphInstantiate");
+        }
+        w->graphs.push_back(GraphEntry{u->uid, prm->solver, ip, N, K, gr, exec});
       }
-      LQCD_HIP(hipGraphLaunch(gc.exec, st));
+      LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;
     }
     for (int i = 0; i < K; ++i) LQCD_HIP(iteration(i));
