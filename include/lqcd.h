@@ -174,6 +174,38 @@ int lqcd_dw_apply(const lqcd_gauge_t *u, const lqcd_dirac *d, int op, int prec, 
  * parities in precision prec. */
 size_t lqcd_vec_bytes(const lqcd_geom_t *g, int prec, int nrhs, int nparity);
 
+/* ---- kernel tuning (autotuner) ------------------------------------------ */
+typedef struct lqcd_tuning {
+  int32_t nr_tile;     /* right-hand sides per thread in the hop kernels: 1..4 */
+  int32_t block_order; /* workgroup -> sites: 0 plain; 1 every XCD walks a
+                          contiguous range; 2 every XCD owns a z-slab and walks
+                          it plane by plane in t (needs Lz % 8 == 0 and a
+                          whole number of workgroups per (z, t) plane, else 1
+                          is used); 3 and 4 as 1 and 2 with the rhs tiles one
+                          after the other */
+  int32_t rhs_lanes;   /* lanes sharing one site, each with its own nr_tile
+                          rhs: 1, 2 or 4 (FP64 uses 1) */
+  int32_t reserved;
+} lqcd_tuning;
+
+/* Hop-kernel configuration used by a workspace for precision `prec`
+ * (default: nr_tile 1, block_order 1, rhs_lanes 1).  A launch over n rhs uses
+ * the largest rhs_lanes and nr_tile not above these whose product divides n.
+ * EINVAL for values out of range.  None of these changes the arithmetic of
+ * any rhs. */
+int lqcd_ws_set_tuning(lqcd_ws_t *w, int prec, const lqcd_tuning *t);
+int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
+
+/* Autotuner: times every candidate configuration (nr_tile x rhs_lanes
+ * dividing nrhs, block_order) of one Schur-operator application (both hop kernels)
+ * in precision `prec` on nrhs fields of the workspace, with HIP events on
+ * `stream`, at the workspace's real lattice shape; stores the fastest in the
+ * workspace and returns it with its time in microseconds.  Overwrites the
+ * workspace's vectors (not its clover term).  Requires nrhs <= the
+ * workspace's nrhs and `prec` held by gauge field and workspace. */
+int lqcd_autotune(const lqcd_gauge_t *u, const lqcd_dirac *d, int prec, int nrhs, lqcd_ws_t *w,
+                  void *stream, lqcd_tuning *best, double *best_us);
+
 /* ---- solver (paper Sec. 3.3: CG!, propagator!) ------------------------- */
 enum {
   LQCD_SOLVER_CG_FULL = 0, /* CG on Dw^+ Dw over the full lattice */
@@ -212,6 +244,62 @@ typedef struct lqcd_solve_info {
  * entries. */
 int lqcd_solve(const lqcd_gauge_t *u, const lqcd_solve_params *p, const void *eta,
                void *psi, lqcd_ws_t *w, void *stream, lqcd_solve_info *info);
+
+/* ---- serving: continuous batching of propagator solves ------------------ */
+/* A server keeps gauge fields resident in a caller-provided device arena and
+ * runs solve requests as they arrive.  `max_streams` worker threads, each with
+ * its own HIP stream, take requests from a queue; a request is admitted when
+ * a worker is free and its device footprint (workspace + source/solution
+ * staging, lqcd_request_bytes) fits in the free part of the arena.  Requests
+ * behind a head that does not fit may be admitted first (at most 8 times in a
+ * row, so the head is not starved).  Kernels of different requests overlap on
+ * the device.  Every request's result is the same as the same solve alone:
+ * requests share only read-only gauge fields.  The paper runs independent
+ * jobs side by side across GPUs (Sec. 1) and keeps fields and workspaces
+ * resident on the device (Sec. 2.2); here the independent jobs are requests
+ * sharing one GPU. */
+typedef struct lqcd_server lqcd_server_t;
+
+enum { LQCD_ECANCELED = -9 }; /* request cancelled by lqcd_server_destroy */
+
+/* arena: device memory (>= 256-byte aligned) owned by the caller, used for
+ * gauge fields and request workspaces; max_streams in [1, 16]; queue_cap >= 1
+ * bounds the queued (not yet admitted) requests.  With arena == NULL the
+ * server runs in simulation mode: no device work at all, each admitted
+ * request holds its footprint for sim_seconds and completes with status OK
+ * (for testing the scheduler without a GPU); sim_seconds is ignored
+ * otherwise. */
+int lqcd_server_create(void *arena, size_t arena_bytes, int max_streams, int queue_cap,
+                       double sim_seconds, lqcd_server_t **out);
+/* Registers a gauge field: U is canonical complex128 in host memory, copied
+ * into the arena in FP64 and the precisions of pmask.  Returns its id. */
+int lqcd_server_add_gauge(lqcd_server_t *s, const lqcd_geom_desc *desc, const void *U_host,
+                          int pmask, int *gauge_id);
+/* Device bytes one request with these parameters holds while it runs. */
+size_t lqcd_request_bytes(lqcd_server_t *s, int gauge_id, const lqcd_solve_params *p);
+/* Enqueues Dw psi = eta for gauge_id (thread-safe, non-blocking).  eta and
+ * psi are canonical complex128 host buffers of p->nrhs fields that must stay
+ * valid until lqcd_poll returns a final status.  EBUSY if the queue is full,
+ * ENOMEM if the request can never fit in the arena, ENOTFOUND for an unknown
+ * gauge id. */
+int lqcd_submit(lqcd_server_t *s, int gauge_id, const lqcd_solve_params *p, const void *eta,
+                void *psi, uint64_t *ticket);
+/* PENDING while the request is queued or running; otherwise its final
+ * status (as lqcd_solve, or ECANCELED), with info[nrhs] filled and, if times
+ * is not NULL, times[0..2] = submit, admission and completion times in
+ * seconds since the server was created.  A final status releases the ticket
+ * (later polls return ENOTFOUND).  Thread-safe. */
+int lqcd_poll(lqcd_server_t *s, uint64_t ticket, lqcd_solve_info *info, double *times);
+/* Peak bytes of the arena in use since creation. */
+size_t lqcd_server_peak_bytes(lqcd_server_t *s);
+/* Stops the server: no further submissions; with cancel_pending, queued
+ * requests end with ECANCELED, otherwise they are run first; running
+ * requests always finish.  Returns once the workers have exited; tickets can
+ * still be polled afterwards. */
+int lqcd_server_stop(lqcd_server_t *s, int cancel_pending);
+/* lqcd_server_stop (if not yet stopped), then frees the handle, its gauge
+ * fields and any unpolled tickets. */
+int lqcd_server_destroy(lqcd_server_t *s, int cancel_pending);
 
 #ifdef __cplusplus
 }

@@ -1,38 +1,30 @@
 // Hopping-term (Wilson "Dslash") kernels with the clover block fused in.
 //
-// One thread owns one output site of parity p_out and NR right-hand sides.
-// For each of the 8 hops it loads the link once (9 site-coalesced complex
-// loads), and for each of its NR rhs the neighbour spinor (12 loads), spin
-// projects it to a half spinor, multiplies by U or U^+ and accumulates the
-// reconstructed full spinor.  The clover block (two Hermitian 6x6 blocks,
-// 36 complex loads) is likewise read once per thread for all NR rhs.  The
-// only cross-lane work is the optional |out|^2 block reduction (wave64
-// butterfly + LDS across the block's waves), which is deterministic.
+// Work decomposition.  A thread owns one output site of parity p_out and NR
+// right-hand sides; RL consecutive lanes share one site and own RL different
+// rhs groups (so a 256-thread block covers 256/RL sites and RL*NR rhs).  Per
+// hop a thread loads the link (9 site-coalesced complex loads; the RL lanes of
+// a site issue identical addresses, which the memory pipeline serves once)
+// and, for each of its NR rhs, the neighbour spinor (12 loads), spin-projects
+// it to a half spinor, multiplies by U or U^+ and accumulates.  The clover
+// blocks (two Hermitian 6x6 blocks) are loaded one chirality at a time and
+// applied to all NR rhs.  Links and clover blocks are read once per launch, so
+// they are loaded non-temporally, leaving L2 to the spinors that neighbouring
+// sites re-read.  The only cross-lane work is the optional per-rhs |out|^2
+// block reduction (wave64 butterfly over the lanes of one rhs, then LDS
+// across the block's waves), which is deterministic.
 //
 // This is a 3x3 complex mat-vec stencil: there is no dense contraction to
-// give to the matrix cores, so the kernel is bound by HBM bandwidth and is
-// written for coalescing (unit-stride SoA loads over sites) and occupancy.
+// give to the matrix cores; the kernel is bound by HBM bandwidth and is
+// written for coalescing (unit-stride SoA loads over sites), L2 reuse (the
+// block orders below) and occupancy (RL instead of NR keeps registers low).
+#include <type_traits>
+
 #include "lqcd_kernels.h"
 
 namespace lqcd {
 
 constexpr int kHopBlock = 256;
-
-template <int BS>
-__device__ inline double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < BS / 64; ++i) s += sh[i];
-  }
-  return s;
-}
 
 template <int MU, int DIR, int NR, typename A, typename SG, typename SI>
 __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, const SI* yb, int p,
@@ -57,7 +49,10 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
                            : Ub + (size_t)(((1 - p) * 4 + MU) * 9) * V2 + sn;
   cpx<A> U[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) U[e] = ld(up + e * V2);
+  for (int e = 0; e < 9; ++e) {
+    auto v = ld_nt(up + e * V2);
+    U[e] = {(A)v.re, (A)v.im};
+  }
 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -87,32 +82,107 @@ template <typename A, typename SG>
 __device__ inline void load_block(const SG* C, int blk, size_t V2, int s, cpx<A> (&m)[18]) {
 #pragma unroll
   for (int e = 0; e < 18; ++e) {
-    auto v = ld(C + (size_t)(blk * 18 + e) * V2 + s);
+    auto v = ld_nt(C + (size_t)(blk * 18 + e) * V2 + s);
     m[e] = {(A)v.re, (A)v.im};
   }
 }
 
-template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR>
+// Mapping of the 1-D grid (nbs site blocks x ntiles rhs tiles) to work.
+// Workgroup b runs on XCD b mod 8 (round-robin dispatch), each XCD with its
+// own L2.
+//   order 0: site block b mod nbs, rhs tile b / nbs (plain order);
+//   order 1: XCD-contiguous: every XCD walks one contiguous range of
+//            (site block, tile) pairs with the tiles of a site block adjacent;
+//   order 2: XCD z-slabs: XCD x owns z-planes [x Lz/8, (x+1) Lz/8) for all t;
+//            it walks, innermost first, the rhs tiles, the site blocks of a
+//            (z, t) plane, the planes of its slab, then t.  The t-neighbours
+//            of a site are then a slab plane (a few blocks) away.  Requires
+//            Lz % 8 == 0 and a whole number of site blocks per (z, t) plane
+//            (else order 1).
+//   order 3: as 1, with the rhs tile outermost (the whole lattice per tile);
+//   order 4: as 2, with the rhs tile outermost.
+// Tile-inner orders read each link once for all tiles but need a reuse window
+// holding all rhs; tile-outer orders read the links once per tile and keep
+// the reuse window of a single tile.
+__device__ inline void block_order(const HopLaunch& a, int b, int nb, int ntiles, int& sb, int& tile) {
+  if (a.order == 0) {
+    sb = b % a.nbs;
+    tile = b / a.nbs;
+    return;
+  }
+  const int x = b & 7, j = b >> 3;
+  if (a.order == 3) {
+    const int l = xcd_remap(b, nb);
+    tile = l / a.nbs;
+    sb = l % a.nbs;
+    return;
+  }
+  if (a.order == 2 || a.order == 4) {
+    const int bpp = a.bpp, zs = a.g.L[2] >> 3;
+    int q;
+    if (a.order == 2) {
+      tile = j % ntiles;
+      q = j / ntiles;
+    } else {
+      const int per_tile = a.nbs >> 3;  // site blocks per XCD and tile
+      tile = j / per_tile;
+      q = j % per_tile;
+    }
+    const int pb = q % bpp;
+    q /= bpp;
+    const int zl = q % zs;
+    const int t = q / zs;
+    sb = pb + bpp * (x * zs + zl + a.g.L[2] * t);
+    return;
+  }
+  const int l = xcd_remap(b, nb);
+  tile = l % ntiles;
+  sb = l / ntiles;
+}
+
+// per-rhs block sum: lanes l and l' hold the same rhs iff l = l' mod RL
+template <int RL>
+__device__ inline double block_sum_rl(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off >= RL; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l < RL) sh[w * RL + l] = v;
+  __syncthreads();
+  double s = 0.0;
+  if ((int)threadIdx.x < RL) {
+#pragma unroll
+    for (int i = 0; i < kHopBlock / 64; ++i) s += sh[i * RL + threadIdx.x];
+  }
+  return s;
+}
+
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL>
 __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
-  __shared__ double red[kHopBlock / 64];
+  constexpr int SPB = kHopBlock / RL;  // sites per block
+  __shared__ double red[(kHopBlock / 64) * RL];
   const KGeom& g = a.g;
-  const int rhs0 = blockIdx.y * NR;
+  // decode (site block, rhs tile) from the 1-D grid; see block_order()
+  int sb, tile;
+  block_order(a, blockIdx.x, gridDim.x, a.nrhs / (NR * RL), sb, tile);
+  const int lane_r = (RL > 1) ? (int)(threadIdx.x % RL) : 0;
+  const int rhs_tile0 = tile * NR * RL;
+  const int rhs0 = rhs_tile0 + lane_r * NR;  // this lane's first rhs
   if (a.done) {
     bool all = true;
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      all = all && (a.done[(rhs0 + r) * (int)(sizeof(CGState) / sizeof(int))] != 0);
+    for (int r = 0; r < NR * RL; ++r)
+      all = all && (a.done[(rhs_tile0 + r) * (int)(sizeof(CGState) / sizeof(int))] != 0);
     if (all) return;
   }
   // parity of this block's output sites and its site index
-  int p = a.p_out, bx = blockIdx.x;
+  int p = a.p_out, bx = sb;
   if (a.both) {
-    const int nbh = gridDim.x >> 1;
+    const int nbh = a.nbs >> 1;
     p = (bx >= nbh) ? 1 : 0;
     bx -= p * nbh;
   }
-  const int s = bx * kHopBlock + threadIdx.x;
+  const int s = bx * SPB + (int)(threadIdx.x / RL);
   const bool active = s < g.V2;
   const size_t V2 = (size_t)g.V2;
   const SI* yb = static_cast<const SI*>(a.y);
@@ -152,129 +222,169 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   const bool masked = (g.bc == BC_SF) && (c.t == 0);
   const A scale = (A)a.scale;
 
-  cpx<A> Cm[2][18];
-  if (active && PRE == PRE_CLOV) {
-    load_block(cpre, 0, V2, s, Cm[0]);
-    load_block(cpre, 1, V2, s, Cm[1]);
+  // v[r] = scale * H y  (+ pre(z)), then post; the clover blocks are loaded
+  // one chirality at a time and applied to all NR rhs of the thread
+  cpx<A> v[NR][12];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[r][k] = cscale(scale, acc[r][k / 3][k % 3]);
+  if (active && PRE != PRE_NONE) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cpx<A> Cm[18];
+      if (PRE == PRE_CLOV) load_block(cpre, b, V2, s, Cm);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const SI* zp = zb + (size_t)(rhs0 + r) * a.z_rs + s;
+        cpx<A> in6[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          auto t = ld(zp + (6 * b + i) * V2);
+          in6[i] = {(A)t.re, (A)t.im};
+        }
+        if (PRE == PRE_IDENT) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) v[r][6 * b + i] = cadd(v[r][6 * b + i], in6[i]);
+        } else {
+          cpx<A> o6[6];
+          herm6_mul(Cm, in6, o6);
+#pragma unroll
+          for (int i = 0; i < 6; ++i) v[r][6 * b + i] = cadd(v[r][6 * b + i], o6[i]);
+        }
+      }
+    }
   }
-  cpx<A> Ci[2][18];
   if (active && POST == POST_CLOV) {
-    load_block(static_cast<const SG*>(a.Cpost), 0, V2, s, Ci[0]);
-    load_block(static_cast<const SG*>(a.Cpost), 1, V2, s, Ci[1]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cpx<A> Ci[18];
+      load_block(static_cast<const SG*>(a.Cpost), b, V2, s, Ci);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        cpx<A> in6[6], o6[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) in6[i] = v[r][6 * b + i];
+        herm6_mul(Ci, in6, o6);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[r][6 * b + i] = o6[i];
+      }
+    }
   }
 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     double nrm = 0.0;
     if (active) {
-      cpx<A> v[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] = cscale(scale, acc[r][k / 3][k % 3]);
-      if (PRE != PRE_NONE) {
-        const SI* zp = zb + (size_t)(rhs0 + r) * a.z_rs + s;
-        cpx<A> zv[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          auto t = ld(zp + k * V2);
-          zv[k] = {(A)t.re, (A)t.im};
-        }
-        if (PRE == PRE_IDENT) {
-#pragma unroll
-          for (int k = 0; k < 12; ++k) v[k] = cadd(v[k], zv[k]);
-        } else {
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            cpx<A> in6[6], o6[6];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) in6[i] = zv[6 * b + i];
-            herm6_mul(Cm[b], in6, o6);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) v[6 * b + i] = cadd(v[6 * b + i], o6[i]);
-          }
-        }
-      }
-      if (POST == POST_CLOV) {
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cpx<A> in6[6], o6[6];
-#pragma unroll
-          for (int i = 0; i < 6; ++i) in6[i] = v[6 * b + i];
-          herm6_mul(Ci[b], in6, o6);
-#pragma unroll
-          for (int i = 0; i < 6; ++i) v[6 * b + i] = o6[i];
-        }
-      }
       if (a.g5) {
 #pragma unroll
-        for (int k = 6; k < 12; ++k) v[k] = {-v[k].re, -v[k].im};
+        for (int k = 6; k < 12; ++k) v[r][k] = {-v[r][k].re, -v[r][k].im};
       }
       if (masked) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = {(A)0, (A)0};
+        for (int k = 0; k < 12; ++k) v[r][k] = {(A)0, (A)0};
       }
       SO* op = ob + (size_t)(rhs0 + r) * a.out_rs + s;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) st(op + k * V2, v[k]);
+      for (int k = 0; k < 12; ++k) st(op + k * V2, v[r][k]);
       if (a.partials) {
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-          nrm += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+          nrm += (double)v[r][k].re * (double)v[r][k].re + (double)v[r][k].im * (double)v[r][k].im;
       }
     }
     if (a.partials) {
-      double bs = block_sum<kHopBlock>(nrm, red);
-      if (threadIdx.x == 0) a.partials[(size_t)(rhs0 + r) * gridDim.x + blockIdx.x] = bs;
+      const double bs = block_sum_rl<RL>(nrm, red);
+      if ((int)threadIdx.x < RL)
+        a.partials[(size_t)(rhs_tile0 + (int)threadIdx.x * NR + r) * a.nbs + sb] = bs;
     }
   }
 }
 
+static int sites_per_block(int rl) { return kHopBlock / (rl < 1 ? 1 : rl); }
+
 int hop_nblocks(const HopLaunch& h) {
-  const int nb = (h.g.V2 + kHopBlock - 1) / kHopBlock;
+  const int spb = sites_per_block(h.rhs_lanes);
+  const int nb = (h.g.V2 + spb - 1) / spb;
   return h.both ? 2 * nb : nb;
 }
 
-template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP>
-static hipError_t launch_nr(const HopLaunch& h, hipStream_t st) {
-  const int nb = hop_nblocks(h);
-  const int nr = h.nr_tile;
-  if (h.nrhs % nr != 0) return hipErrorInvalidValue;
-  dim3 grid(nb, h.nrhs / nr);
-  switch (nr) {
-    case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 4: k_hop<SG, SI, SO, PRE, POST, HOP, 4><<<grid, kHopBlock, 0, st>>>(h); break;
+// fill in nbs/bpp and validate the block order for this launch
+static bool prepare(HopLaunch& h) {
+  if (h.rhs_lanes != 1 && h.rhs_lanes != 2 && h.rhs_lanes != 4) return false;
+  if (h.nr_tile < 1 || h.nr_tile > 4) return false;
+  if (h.nrhs % (h.nr_tile * h.rhs_lanes) != 0) return false;
+  h.nbs = hop_nblocks(h);
+  const int spb = sites_per_block(h.rhs_lanes);
+  const long P = (long)h.g.Lxh * h.g.L[1];
+  h.bpp = (int)(P / spb);
+  const bool slab_ok = !h.both && (h.g.L[2] % 8) == 0 && (P % spb) == 0;
+  if (h.order == 2 && !slab_ok) h.order = 1;
+  if (h.order == 4 && !slab_ok) h.order = 3;
+  if (h.order < 0 || h.order > 4) h.order = 1;
+  return true;
+}
+
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int RL>
+static hipError_t launch_rl(const HopLaunch& h, hipStream_t st) {
+  const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
+  switch (h.nr_tile) {
+    case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 4: k_hop<SG, SI, SO, PRE, POST, HOP, 4, RL><<<grid, kHopBlock, 0, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// the two hot shapes: every (nr_tile, rhs_lanes); FP64 only with rhs_lanes 1
 template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP>
-static hipError_t launch_nr1(const HopLaunch& h, hipStream_t st) {
-  if (h.nr_tile != 1) return hipErrorInvalidValue;
-  dim3 grid(hop_nblocks(h), h.nrhs);
-  k_hop<SG, SI, SO, PRE, POST, HOP, 1><<<grid, kHopBlock, 0, st>>>(h);
+static hipError_t launch_tiled(const HopLaunch& h0, hipStream_t st) {
+  HopLaunch h = h0;
+  if (std::is_same<SG, double2>::value) h.rhs_lanes = 1;
+  if (!prepare(h)) return hipErrorInvalidValue;
+  if constexpr (std::is_same<SG, double2>::value) {
+    return launch_rl<SG, SI, SO, PRE, POST, HOP, 1>(h, st);
+  } else {
+    switch (h.rhs_lanes) {
+      case 1: return launch_rl<SG, SI, SO, PRE, POST, HOP, 1>(h, st);
+      case 2: return launch_rl<SG, SI, SO, PRE, POST, HOP, 2>(h, st);
+      case 4: return launch_rl<SG, SI, SO, PRE, POST, HOP, 4>(h, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+// set-up shapes (source preparation, reconstruction, block application):
+// one rhs per thread
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP>
+static hipError_t launch_single(const HopLaunch& h0, hipStream_t st) {
+  HopLaunch h = h0;
+  h.nr_tile = 1;
+  h.rhs_lanes = 1;
+  if (!prepare(h)) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)h.nbs * (unsigned)h.nrhs;
+  k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1><<<grid, kHopBlock, 0, st>>>(h);
   return hipGetLastError();
 }
 
-// Dispatch on the operator shape; the two hot shapes (e->o with the clover
-// inverse after, o->e with the clover before) get every rhs tile.
 template <typename SG, typename SI, typename SO>
 static hipError_t dispatch_mode(const HopLaunch& h, hipStream_t st) {
   if (h.hop && h.pre == PRE_NONE && h.post == POST_CLOV)
-    return launch_nr<SG, SI, SO, PRE_NONE, POST_CLOV, true>(h, st);
+    return launch_tiled<SG, SI, SO, PRE_NONE, POST_CLOV, true>(h, st);
   if (h.hop && h.pre == PRE_CLOV && h.post == POST_NONE)
-    return launch_nr<SG, SI, SO, PRE_CLOV, POST_NONE, true>(h, st);
+    return launch_tiled<SG, SI, SO, PRE_CLOV, POST_NONE, true>(h, st);
   if (h.hop && h.pre == PRE_IDENT && h.post == POST_NONE)
-    return launch_nr1<SG, SI, SO, PRE_IDENT, POST_NONE, true>(h, st);
+    return launch_single<SG, SI, SO, PRE_IDENT, POST_NONE, true>(h, st);
   if (h.hop && h.pre == PRE_IDENT && h.post == POST_CLOV)
-    return launch_nr1<SG, SI, SO, PRE_IDENT, POST_CLOV, true>(h, st);
+    return launch_single<SG, SI, SO, PRE_IDENT, POST_CLOV, true>(h, st);
   if (!h.hop && h.pre == PRE_IDENT && h.post == POST_CLOV)
-    return launch_nr1<SG, SI, SO, PRE_IDENT, POST_CLOV, false>(h, st);
+    return launch_single<SG, SI, SO, PRE_IDENT, POST_CLOV, false>(h, st);
   if (!h.hop && h.pre == PRE_CLOV && h.post == POST_NONE)
-    return launch_nr1<SG, SI, SO, PRE_CLOV, POST_NONE, false>(h, st);
+    return launch_single<SG, SI, SO, PRE_CLOV, POST_NONE, false>(h, st);
   if (h.hop && h.pre == PRE_NONE && h.post == POST_NONE)
-    return launch_nr1<SG, SI, SO, PRE_NONE, POST_NONE, true>(h, st);
+    return launch_single<SG, SI, SO, PRE_NONE, POST_NONE, true>(h, st);
   return hipErrorInvalidValue;
 }
 

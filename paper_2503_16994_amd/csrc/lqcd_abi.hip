@@ -350,8 +350,8 @@ static HopLaunch base_launch(const OpCtx& c) {
   h.prec = h.in_prec = h.out_prec = c.prec;
   h.U = links_of(c.u, c.prec);
   h.nrhs = c.nrhs;
-  h.nr_tile = 1;
   h.hop = true;
+  apply_tuning(h, c.w->tune[c.prec]);
   return h;
 }
 
@@ -497,5 +497,87 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
     }
   }
   if (canon) LQCD_HIP(launch_unpack(g->kg, vout, prec, (double2*)out, nrhs, st));
+  return LQCD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+extern "C" int lqcd_ws_set_tuning(lqcd_ws_t* w, int prec, const lqcd_tuning* t) {
+  if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: null pointer");
+  if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: bad precision %d", prec);
+  if (t->nr_tile < 1 || t->nr_tile > 4 || t->block_order < 0 || t->block_order > 4 ||
+      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4))
+    return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: value out of range");
+  w->tune[prec] = *t;
+  w->tune[prec].reserved = 0;
+  return LQCD_OK;
+}
+
+extern "C" int lqcd_ws_get_tuning(const lqcd_ws_t* w, int prec, lqcd_tuning* t) {
+  if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_get_tuning: null pointer");
+  if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_get_tuning: bad precision %d", prec);
+  *t = w->tune[prec];
+  return LQCD_OK;
+}
+
+extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int prec, int nrhs, lqcd_ws_t* w,
+                             void* stream, lqcd_tuning* best, double* best_us) {
+  if (!u || !d || !w) return fail(LQCD_EINVAL, "lqcd_autotune: null pointer");
+  if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_autotune: bad precision %d", prec);
+  if (nrhs < 1 || nrhs > w->nrhs) return fail(LQCD_EINVAL, "lqcd_autotune: nrhs=%d (workspace %d)", nrhs, w->nrhs);
+  const int pbit = 1 << prec;
+  if (!(u->pmask & pbit) || !(w->pmask & pbit))
+    return fail(LQCD_EINVAL, "lqcd_autotune: precision %d not held by gauge field and workspace", prec);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_clover(u, d, w, st);
+  if (rc) return rc;
+  // operands: two full-layout vectors of the FP64 slots (wide enough for any precision)
+  const size_t full_bytes = (size_t)nrhs * 24 * w->g->V2 * elem_bytes(prec);
+  LQCD_HIP(launch_fill_zero(w->m.X, full_bytes, st));
+  hipEvent_t e0, e1;
+  LQCD_HIP(hipEventCreate(&e0));
+  LQCD_HIP(hipEventCreate(&e1));
+  const lqcd_tuning saved = w->tune[prec];
+  double best_t = 1e300;
+  lqcd_tuning best_cfg = saved;
+  OpCtx c{u, w, prec, nrhs, st};
+  hipError_t err = hipSuccess;
+  for (int rl = 1; rl <= 4 && err == hipSuccess; rl *= 2) {
+    if (nrhs % rl || (prec == P_F64 && rl > 1)) continue;
+    for (int nr = 1; nr <= 4 && err == hipSuccess; ++nr) {
+      if (nrhs % (nr * rl)) continue;
+      for (int order = 0; order <= 4 && err == hipSuccess; ++order) {
+        w->tune[prec] = lqcd_tuning{nr, order, rl, 0};
+        auto once = [&]() -> hipError_t {
+          hipError_t e = apply_hop_eo(c, w->m.X, w->m.R);
+          if (e == hipSuccess) e = apply_hop_oe(c, w->m.X, w->m.R, w->m.TMP, false, nullptr);
+          return e;
+        };
+        for (int i = 0; i < 2 && err == hipSuccess; ++i) err = once();
+        if (err == hipSuccess) err = hipEventRecord(e0, st);
+        const int reps = 6;
+        for (int i = 0; i < reps && err == hipSuccess; ++i) err = once();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps;
+        if (err == hipSuccess && us < best_t) {
+          best_t = us;
+          best_cfg = w->tune[prec];
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) {
+    w->tune[prec] = saved;
+    return hip_status(err, "lqcd_autotune");
+  }
+  w->tune[prec] = best_cfg;
+  if (best) *best = best_cfg;
+  if (best_us) *best_us = best_t;
   return LQCD_OK;
 }

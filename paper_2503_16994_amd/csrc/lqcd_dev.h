@@ -105,6 +105,35 @@ template <typename S>
 __device__ inline auto ld(const S* p) {
   return StoreTraits<S>::load(p);
 }
+
+// Non-temporal load (read-once data: links, clover blocks).  The streaming
+// hint keeps such lines from displacing the spinor lines that neighbouring
+// sites re-read from L2.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ inline cpx<double> ld_nt(const double2* p) {
+  nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return {v.x, v.y};
+}
+__device__ inline cpx<float> ld_nt(const float2* p) {
+  nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return {v.x, v.y};
+}
+__device__ inline cpx<float> ld_nt(const bf16x2* p) {
+  uint32_t v = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+  return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+}
+
+// Block index remap for the 8 XCDs of the MI355X.  Workgroups are handed to
+// the XCDs round-robin (workgroup b runs on XCD b mod 8, each XCD with its own
+// L2); this maps the b-th workgroup to logical block
+//   start(b mod 8) + b/8,  start(x) = x*floor(nb/8) + min(x, nb mod 8),
+// a bijection on [0, nb) under which every XCD walks one contiguous range of
+// sites, so the y, z and t neighbours of its sites are mostly its own.
+__device__ inline int xcd_remap(int b, int nb) {
+  const int x = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + j;
+}
 template <typename S, typename A>
 __device__ inline void st(S* p, cpx<A> c) {
   StoreTraits<S>::store(p, c);

@@ -68,6 +68,7 @@ struct lqcd_ws {
   double kappa = 0, csw = 0, cF = 0;
   int clover_pmask = 0;
   std::vector<GraphEntry> graphs;
+  lqcd_tuning tune[3] = {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}};  // nr, order, lanes
 };
 
 namespace lqcd {
@@ -99,5 +100,21 @@ struct HopSpec {
   bool g5 = false;
   double scale = 0.0;
 };
+
+// rhs tiling of a launch over nrhs fields: rhs_lanes lanes per site, each
+// with nr_tile rhs; both are reduced until their product divides nrhs
+inline void apply_tuning(HopLaunch& h, const lqcd_tuning& t) {
+  int rl = (t.rhs_lanes == 2 || t.rhs_lanes == 4) ? t.rhs_lanes : 1;
+  int nr = t.nr_tile < 1 ? 1 : (t.nr_tile > 4 ? 4 : t.nr_tile);
+  while (h.nrhs % rl) rl >>= 1;
+  while (h.nrhs % (nr * rl)) --nr;
+  h.nr_tile = nr;
+  h.rhs_lanes = rl;
+  h.order = t.block_order;
+}
+inline void single_tile(HopLaunch& h) {
+  h.nr_tile = 1;
+  h.rhs_lanes = 1;
+}
 
 }  // namespace lqcd

@@ -51,6 +51,13 @@ struct HopLaunch {
   bool both;
   long par_stride;
   long cpre_par;
+  // tuning: block order (0..4, see block_order in k_dslash.hip) and the
+  // number of lanes that share a site and split its rhs (1, 2, 4)
+  int order;
+  int rhs_lanes;
+  // filled in by the launcher
+  int nbs;  // site blocks (both parities in `both` mode)
+  int bpp;  // site blocks per (z, t) plane
 };
 
 int hop_nblocks(const HopLaunch& h);

@@ -79,8 +79,8 @@ HopLaunch mk(const Ctl& c, int lprec) {
   h.prec = lprec;
   h.U = links_of(c.u, lprec);
   h.nrhs = c.nrhs;
-  h.nr_tile = 1;
   h.hop = true;
+  apply_tuning(h, c.w->tune[lprec]);
   return h;
 }
 
@@ -99,7 +99,7 @@ hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, in
   h.post = POST_CLOV;
   h.scale = -0.5;
   h.done = done;
-  h.nr_tile = nr_tile;
+  if (nr_tile == 1) single_tile(h);
   return launch_hop(h, c.st);
 }
 
@@ -123,7 +123,7 @@ hipError_t hop_oe(const Ctl& c, int lprec, Vec z, Vec t_o, Vec out, bool g5, dou
   h.g5 = g5;
   h.partials = partials;
   h.done = done;
-  h.nr_tile = nr_tile;
+  if (nr_tile == 1) single_tile(h);
   return launch_hop(h, c.st);
 }
 
@@ -304,7 +304,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   }
   const int lprec = mixed ? ip : P_F64;
   const int nb_blas = blas_nblocks(n_vec);
-  const int nr_tile = 1;
+  const int nr_tile = 0;  // 0: the workspace's tuned tile
 
   CGSetup cfg;
   cfg.nrhs = N;

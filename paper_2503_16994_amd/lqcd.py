@@ -57,6 +57,14 @@ class SolveParams(ctypes.Structure):
                 ("tol", ctypes.c_double), ("nrhs", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("nr_tile", ctypes.c_int32), ("block_order", ctypes.c_int32),
+                ("rhs_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"nr_tile": self.nr_tile, "block_order": self.block_order, "rhs_lanes": self.rhs_lanes}
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("restarts", ctypes.c_int32),
@@ -86,7 +94,20 @@ SIGNATURES = {
     "lqcd_dw_apply": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _I, _I, _P, _P, _P, _P]),
     "lqcd_vec_bytes": (_Z, [_P, _I, _I, _I]),
     "lqcd_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
+    "lqcd_ws_set_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
+    "lqcd_ws_get_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
+    "lqcd_autotune": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _P, _P, ctypes.POINTER(Tuning),
+                           ctypes.POINTER(ctypes.c_double)]),
+    "lqcd_server_create": (_I, [_P, _Z, _I, _I, _D, ctypes.POINTER(_P)]),
+    "lqcd_server_add_gauge": (_I, [_P, ctypes.POINTER(GeomDesc), _P, _I, ctypes.POINTER(_I)]),
+    "lqcd_request_bytes": (_Z, [_P, _I, ctypes.POINTER(SolveParams)]),
+    "lqcd_submit": (_I, [_P, _I, ctypes.POINTER(SolveParams), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "lqcd_poll": (_I, [_P, ctypes.c_uint64, _P, _P]),
+    "lqcd_server_peak_bytes": (_Z, [_P]),
+    "lqcd_server_stop": (_I, [_P, _I]),
+    "lqcd_server_destroy": (_I, [_P, _I]),
 }
+ECANCELED = -9
 
 
 def lib():
@@ -239,6 +260,27 @@ def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torc
                                ws.handle, _stream_ptr(stream)))
 
 
+def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1):
+    t = Tuning(int(nr_tile), int(block_order), int(rhs_lanes), 0)
+    _check(lib().lqcd_ws_set_tuning(ws.handle, prec, ctypes.byref(t)))
+
+
+def get_tuning(ws: Workspace, prec) -> dict:
+    t = Tuning()
+    _check(lib().lqcd_ws_get_tuning(ws.handle, prec, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def autotune(gauge: GaugeField, d: Dirac, prec, nrhs, ws: Workspace, stream=None):
+    """Time the hop-kernel configurations and keep the fastest in `ws`.
+    Returns (tuning dict, microseconds per Schur-operator application)."""
+    t = Tuning()
+    us = ctypes.c_double(0.0)
+    _check(lib().lqcd_autotune(gauge.handle, ctypes.byref(d), prec, nrhs, ws.handle,
+                               _stream_ptr(stream), ctypes.byref(t), ctypes.byref(us)))
+    return t.as_dict(), us.value
+
+
 def vec_bytes(lat: Lattice, prec, nrhs, nparity=2) -> int:
     return int(lib().lqcd_vec_bytes(lat.handle, prec, nrhs, nparity))
 
@@ -271,3 +313,99 @@ def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, m
         _check(st)
     out = psi[0] if single else psi
     return SolveResult(out, [infos[i].as_dict() for i in range(nrhs)], st)
+
+
+class Server:
+    """Continuous-batching solve server (lqcd_server_*).
+
+    With ``sim_seconds`` set, the server runs in simulation mode (no device
+    memory or work; each request holds its footprint for sim_seconds)."""
+
+    def __init__(self, arena_bytes, max_streams=4, queue_cap=4096, sim_seconds=None):
+        self._mem = None
+        if sim_seconds is None:
+            self._mem = _dev_bytes(arena_bytes)
+            arena = ctypes.c_void_p(_aligned_ptr(self._mem))
+            sim = 0.0
+        else:
+            arena = None
+            sim = float(sim_seconds)
+        h = ctypes.c_void_p()
+        _check(lib().lqcd_server_create(arena, int(arena_bytes), int(max_streams), int(queue_cap), sim,
+                                        ctypes.byref(h)))
+        self.handle = h
+        self._live = {}  # ticket -> (eta, psi, nrhs) kept alive until final
+        self.nrhs_of = {}
+
+    def add_gauge(self, L, bc, theta, U=None, pmask=PM_F64):
+        d = GeomDesc()
+        for i in range(4):
+            d.L[i] = int(L[i])
+            th = complex(theta[i])
+            d.theta_re[i] = th.real
+            d.theta_im[i] = th.imag
+        d.bc = int(bc)
+        ptr = None
+        if U is not None:
+            import numpy as np
+            U = np.ascontiguousarray(U, dtype=np.complex128)
+            ptr = ctypes.c_void_p(U.ctypes.data)
+        gid = ctypes.c_int(-1)
+        _check(lib().lqcd_server_add_gauge(self.handle, ctypes.byref(d), ptr, int(pmask), ctypes.byref(gid)))
+        return gid.value
+
+    @staticmethod
+    def params(kappa, csw, cF=1.0, tol=1e-10, maxiter=20000, inner_prec=F64, nrhs=1, reliable_every=100,
+               use_graph=True):
+        return SolveParams(Dirac(float(kappa), float(csw), float(cF), 0.0), SOLVER_CG_EO, int(inner_prec),
+                           int(reliable_every), int(maxiter), float(tol), int(nrhs), int(bool(use_graph)))
+
+    def request_bytes(self, gauge_id, p: SolveParams) -> int:
+        return int(lib().lqcd_request_bytes(self.handle, int(gauge_id), ctypes.byref(p)))
+
+    def submit(self, gauge_id, p: SolveParams, eta=None, psi=None) -> int:
+        """Enqueue a solve; eta/psi are host complex128 arrays (kept alive here)."""
+        ep = pp = None
+        if eta is not None:
+            import numpy as np
+            eta = np.ascontiguousarray(eta, dtype=np.complex128)
+            if psi is None:
+                psi = np.empty_like(eta)
+            ep, pp = ctypes.c_void_p(eta.ctypes.data), ctypes.c_void_p(psi.ctypes.data)
+        t = ctypes.c_uint64(0)
+        _check(lib().lqcd_submit(self.handle, int(gauge_id), ctypes.byref(p), ep, pp, ctypes.byref(t)))
+        self._live[t.value] = (eta, psi, p.nrhs)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending; else (status, [info dicts], (t_submit, t_admit, t_done), psi)."""
+        eta, psi, nrhs = self._live[ticket]
+        infos = (SolveInfo * nrhs)()
+        times = (ctypes.c_double * 3)()
+        st = lib().lqcd_poll(self.handle, ctypes.c_uint64(ticket), infos, times)
+        if st == PENDING:
+            return None
+        if st == ENOTFOUND:
+            _check(st)
+        del self._live[ticket]
+        return st, [infos[i].as_dict() for i in range(nrhs)], tuple(times), psi
+
+    def poll_raw(self, ticket) -> int:
+        return lib().lqcd_poll(self.handle, ctypes.c_uint64(ticket), None, None)
+
+    def peak_bytes(self) -> int:
+        return int(lib().lqcd_server_peak_bytes(self.handle))
+
+    def stop(self, cancel_pending=False):
+        _check(lib().lqcd_server_stop(self.handle, int(bool(cancel_pending))))
+
+    def close(self, cancel_pending=False):
+        if getattr(self, "handle", None):
+            _check(lib().lqcd_server_destroy(self.handle, int(bool(cancel_pending))))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close(cancel_pending=True)
+        except Exception:
+            pass

@@ -91,3 +91,6 @@ def test_null_and_bad_arguments_are_rejected_without_device_work():
     assert lib.lqcd_gauge_create(None, None, 1, None, 0, None, ctypes.byref(h)) == lqcd.EINVAL
     assert lib.lqcd_ws_create(None, 1, 1, None, 0, ctypes.byref(h)) == lqcd.EINVAL
     assert lib.lqcd_strerror(lqcd.ENOCONV) == b"solver did not converge"
+    t = lqcd.Tuning(1, 1, 0, 0)
+    assert lib.lqcd_ws_set_tuning(None, 0, ctypes.byref(t)) == lqcd.EINVAL
+    assert lib.lqcd_autotune(None, None, 0, 1, None, None, None, None) == lqcd.EINVAL

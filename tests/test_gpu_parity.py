@@ -247,3 +247,36 @@ def test_graph_capture_matches_eager_and_is_deterministic():
         g = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, use_graph=True, stream=stream)
         torch.cuda.synchronize()
         assert np.array_equal(g.psi.cpu().numpy(), eager)
+
+
+def test_tuning_does_not_change_results():
+    """rhs tile, block order and rhs lanes leave every rhs bitwise equal."""
+    # 16x16x8x8: Lz % 8 == 0 and (Lx/2) Ly = 256, so block order 2 is exercised
+    s = Setup((16, 16, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=8,
+              pmask=lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16)
+    eta = torch.from_numpy(np.stack([inputs.gaussian_spinor(s.L, k) for k in range(8)])).cuda()
+    ref = {}
+    for ip in (lqcd.F64, lqcd.F32, lqcd.BF16):
+        for cfg in ((1, 0, 1), (2, 1, 1), (3, 2, 2), (1, 3, 2), (1, 4, 4), (2, 2, 4)):
+            ws = lqcd.Workspace(s.lat, s.gauge.pmask, 8)
+            lqcd.set_tuning(ws, ip, *cfg)
+            assert lqcd.get_tuning(ws, ip)["nr_tile"] == cfg[0]
+            if ip == lqcd.F64 and cfg[2] > 1:
+                continue
+            r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=ip, ws=ws)
+            got = r.psi.cpu().numpy()
+            if ip not in ref:
+                ref[ip] = got
+            assert np.array_equal(got, ref[ip]), (ip, cfg)
+
+
+def test_autotune_picks_a_valid_config():
+    s = Setup((8, 8, 8, 16), P, TH_AP, 0.2, 0.135, 1.9, 1.0, seed=9, pmask=lqcd.PM_F64 | lqcd.PM_F32)
+    ws = lqcd.Workspace(s.lat, s.gauge.pmask, 12)
+    best, us = lqcd.autotune(s.gauge, s.d, lqcd.F32, 12, ws)
+    print("autotune 8^3x16 F32 N=12:", best, f"{us:.1f} us")
+    assert best["nr_tile"] in (1, 2, 3, 4) and us > 0
+    assert lqcd.get_tuning(ws, lqcd.F32) == best
+    eta = torch.from_numpy(inputs.point_sources_12(s.L)).cuda()
+    r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=lqcd.F32, ws=ws)
+    assert r.status == lqcd.OK

@@ -1,0 +1,142 @@
+"""Scheduler of the serving loop, in simulation mode (no GPU): admission by
+device footprint, overlap of admitted requests, arrival-order admission with
+bounded bypass, queue limits, oversize rejection, polling and cancellation."""
+import time
+
+import pytest
+
+from paper_2503_16994_amd import lqcd
+
+L8 = (8, 8, 8, 8)
+TH = (1, 1, 1, -1)
+
+
+def _server(arena, streams=4, cap=64, sim=0.2):
+    return lqcd.Server(arena, max_streams=streams, queue_cap=cap, sim_seconds=sim)
+
+
+def _wait(srv, tickets, timeout=30.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout
+        time.sleep(0.005)
+    return out
+
+
+def test_admission_by_footprint_limits_concurrency():
+    probe = _server(1 << 40)
+    g = probe.add_gauge(L8, 0, TH)
+    p = lqcd.Server.params(0.13, 1.9, nrhs=1)
+    need = probe.request_bytes(g, p)
+    gauge_bytes = probe.peak_bytes()
+    probe.close()
+    # room for the gauge field and exactly two requests
+    srv = _server(gauge_bytes + 2 * need + 1024, streams=4)
+    g = srv.add_gauge(L8, 0, TH)
+    tickets = [srv.submit(g, p) for _ in range(6)]
+    res = _wait(srv, tickets)
+    assert all(r[0] == lqcd.OK for r in res.values())
+    assert srv.peak_bytes() <= gauge_bytes + 2 * need + 1024
+    # at most two requests overlap at any instant, and two do overlap
+    spans = sorted((r[2][1], r[2][2]) for r in res.values())
+    for t in [s[0] + 1e-4 for s in spans]:
+        assert sum(1 for a, b in spans if a <= t < b) <= 2
+    assert spans[1][0] < spans[0][1]
+    srv.close()
+
+
+def test_requests_overlap_up_to_the_worker_count():
+    srv = _server(1 << 40, streams=3, sim=0.3)
+    g = srv.add_gauge(L8, 0, TH)
+    p = lqcd.Server.params(0.13, 1.9)
+    tickets = [srv.submit(g, p) for _ in range(3)]
+    res = _wait(srv, tickets)
+    spans = [(r[2][1], r[2][2]) for r in res.values()]
+    latest_start = max(a for a, _ in spans)
+    earliest_end = min(b for _, b in spans)
+    assert latest_start < earliest_end  # all three ran at the same time
+    srv.close()
+
+
+def test_small_requests_pass_a_blocked_head_with_bounded_bypass():
+    probe = _server(1 << 40)
+    g = probe.add_gauge(L8, 0, TH)
+    small = lqcd.Server.params(0.13, 1.9, nrhs=1)
+    big = lqcd.Server.params(0.13, 1.9, nrhs=12)
+    b_small, b_big = probe.request_bytes(g, small), probe.request_bytes(g, big)
+    gauge_bytes = probe.peak_bytes()
+    probe.close()
+    assert b_big > 2 * b_small
+    # arena: gauge + one big request; a running small request blocks the big one
+    srv = _server(gauge_bytes + b_big + 1024, streams=4, sim=0.15)
+    g = srv.add_gauge(L8, 0, TH)
+    t_first = srv.submit(g, small)
+    time.sleep(0.02)
+    t_big = srv.submit(g, big)
+    t_rest = [srv.submit(g, small) for _ in range(20)]
+    res = _wait(srv, [t_first, t_big] + t_rest, timeout=60)
+    assert all(r[0] == lqcd.OK for r in res.values())
+    admit_big = res[t_big][2][1]
+    passed = sum(1 for t in t_rest if res[t][2][1] < admit_big)
+    assert 1 <= passed <= 8  # some pass the blocked head, but not without bound
+    srv.close()
+
+
+def test_queue_limit_oversize_and_unknown_ids():
+    srv = _server(1 << 30, streams=1, cap=2, sim=0.3)
+    g = srv.add_gauge(L8, 0, TH)
+    p = lqcd.Server.params(0.13, 1.9)
+    t1 = srv.submit(g, p)
+    time.sleep(0.05)  # t1 admitted, queue empty
+    srv.submit(g, p)
+    srv.submit(g, p)
+    with pytest.raises(lqcd.LqcdError) as e:
+        srv.submit(g, p)
+    assert e.value.status == lqcd.EBUSY
+    with pytest.raises(lqcd.LqcdError) as e:
+        srv.submit(g + 7, p)
+    assert e.value.status == lqcd.ENOTFOUND
+    huge = lqcd.Server.params(0.13, 1.9, nrhs=64)
+    big_lat = srv.add_gauge((16, 16, 16, 32), 0, TH)
+    with pytest.raises(lqcd.LqcdError) as e:
+        srv.submit(big_lat, huge)
+    assert e.value.status == lqcd.ENOMEM
+    with pytest.raises(lqcd.LqcdError) as e:
+        srv.submit(g, lqcd.Server.params(-0.1, 1.9))
+    assert e.value.status == lqcd.EINVAL
+    res = _wait(srv, [t1])
+    assert res[t1][0] == lqcd.OK
+    assert srv.poll_raw(t1) == lqcd.ENOTFOUND  # a final poll releases the ticket
+    srv.close()
+
+
+def test_stop_cancels_queued_requests_and_finishes_running_ones():
+    srv = _server(1 << 30, streams=1, cap=16, sim=0.3)
+    g = srv.add_gauge(L8, 0, TH)
+    p = lqcd.Server.params(0.13, 1.9)
+    ts = [srv.submit(g, p) for _ in range(5)]
+    time.sleep(0.05)  # the first is running, four are queued
+    assert srv.poll(ts[-1]) is None
+    srv.stop(cancel_pending=True)
+    res = {t: srv.poll(t) for t in ts}
+    assert res[ts[0]][0] == lqcd.OK
+    assert all(res[t][0] == lqcd.ECANCELED for t in ts[1:])
+    with pytest.raises(lqcd.LqcdError):
+        srv.submit(g, p)
+    srv.close()
+
+
+def test_stop_without_cancel_runs_the_queue():
+    srv = _server(1 << 30, streams=2, cap=16, sim=0.05)
+    g = srv.add_gauge(L8, 0, TH)
+    p = lqcd.Server.params(0.13, 1.9)
+    ts = [srv.submit(g, p) for _ in range(6)]
+    srv.stop(cancel_pending=False)
+    assert all(srv.poll(t)[0] == lqcd.OK for t in ts)
+    srv.close()
