@@ -1,27 +1,35 @@
 #!/usr/bin/env python
 """Benchmark of the Wilson-clover propagator solve on one MI355X.
 
-Workload (one "step"): the 16^3x32 propagator -- links exp(i 0.2 H) (Gaussian
-traceless Hermitian H, seed 2), periodic space / antiperiodic time,
-kappa = 0.1345, csw = 1.9, the 12 spin-colour point sources at the origin
-solved one at a time with the FP64 even-odd preconditioned CG to a true
-relative residual of 1e-10.  Every step runs the whole path: clover term
-(cached per gauge field and parameters after the first call), source
-preparation, CG on Dhat^+ Dhat, odd-site reconstruction and the FP64
-full-lattice residual check.  Inputs are resident in HBM before the timed
-region.
+Workload of the timed step (the value): the 16^3x32 propagator -- links
+exp(i 0.2 H) (Gaussian traceless Hermitian H, seed 2), periodic space /
+antiperiodic time, kappa = 0.1345, csw = 1.9, the 12 spin-colour point
+sources at the origin solved one at a time with the FP64 even-odd
+preconditioned CG to a true relative residual of 1e-10.  Each solve runs the
+whole path: clover term (built once per gauge field and parameters, then
+cached), source preparation, CG on Dhat^+ Dhat in hipGraph chunks, odd-site
+reconstruction and the FP64 full-lattice residual check.  Inputs are
+resident in HBM before the timed region.
 
-Printed JSON line (stdout): value = solves/s of the step; plus
-* "mixed": the same 12 sources as one multi-RHS solve with FP32 (and BF16)
-  inner precision and FP64 reliable updates, solves/s and ratio to FP64;
-* "roofline": the dominant kernel (the FP64 odd->even hop with the clover
-  block applied) -- algorithmic bytes per launch / its average duration,
-  timed with HIP events on the stream it runs on;
-* "dw_hbm": the hop kernels at 32^3x64, whose working set (> 1 GB) does not fit
-  the 256 MB last-level cache, in FP64/FP32/BF16;
-* "cpu_baseline": the FP64 CPU oracle timed on a bounded sample.
+The JSON line (stdout) also carries
+* "mixed": the same 12 sources as one multi-RHS solve, FP32 or BF16 inner
+  precision with FP64 reliable updates (autotuned kernels), vs FP64;
+* "mixed_c4": the 24^3x48 Schroedinger-functional propagator (kappa 0.134,
+  csw 1.8, 12 point sources at t = 1), FP64 one source at a time vs one
+  multi-RHS mixed solve;
+* "c3": the 32^3x64 Z2-noise solve (kappa 0.135) in FP64, FP32 and BF16 inner
+  precision;
+* "roofline": the dominant kernel of the step (the FP64 odd->even hop with
+  the clover block), algorithmic bytes per launch / average launch time
+  (HIP events on its stream);
+* "dw_hbm": the hop kernels at 32^3x64 (working set > 1 GB, beyond the 256 MB
+  last-level cache) in FP64/FP32/BF16;
+* "serving": a Poisson stream of mixed propagator requests through the
+  serving loop, p50/p99 latency and solves/s;
+* "cpu_baseline": the FP64 CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-hbm] [--no-cpu]
+       [--no-mixed] [--no-serve] [--serve-requests N] [--serve-rate R]
 """
 import argparse
 import hashlib
@@ -43,7 +51,7 @@ THETA = (1, 1, 1, -1)
 REALS_HOP_OE = 144   # U 72 + psi_o 12 + psi_e 12 + A_ee 36 + out 12
 REALS_HOP_EO = 132   # U 72 + psi_e 12 + A_oo^-1 36 + out 12
 BYTES_PER_REAL = {0: 8, 1: 4, 2: 2}
-DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1>"
+DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1,1>"
 KERNEL_SOURCES = ["paper_2503_16994_amd/csrc/k_dslash.hip", "paper_2503_16994_amd/csrc/lqcd_dev.h"]
 
 
@@ -87,14 +95,30 @@ def time_launches(fn, reps, stream):
     return e0.elapsed_time(e1) / reps  # ms
 
 
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^3x64 kernel leg")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the 32^3x64 legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only a 1 GiB calibration copy and hop-kernel launches (counter runs)")
     args = ap.parse_args()
@@ -104,7 +128,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -115,19 +138,19 @@ def main():
     if args.profile_kernel:
         profile_kernels(stream)
         return
-
-    # ---- inputs, resident in HBM before timing -------------------------------
-    U = inputs.gauge_field(L_C2, EPS, seed=SEED)
-    lat = lqcd.Lattice(L_C2, lqcd.BC_PERIODIC, THETA)
     pm = lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16
-    gauge = lqcd.GaugeField(lat, torch.from_numpy(U), pm, stream=stream)
+
+    # ---- the step: 16^3x32, 12 sources, FP64 eo-CG one at a time -------------
+    U2 = inputs.gauge_field(L_C2, EPS, seed=SEED)
+    lat = lqcd.Lattice(L_C2, lqcd.BC_PERIODIC, THETA)
+    gauge = lqcd.GaugeField(lat, torch.from_numpy(U2), pm, stream=stream)
     eta = torch.from_numpy(inputs.point_sources_12(L_C2, (0, 0, 0, 0))).cuda()
     psi = torch.empty_like(eta)
     ws1 = lqcd.Workspace(lat, pm, 1)
     ws12 = lqcd.Workspace(lat, pm, 12)
+    d = lqcd.dirac(KAPPA, CSW)
+    tune64, _ = lqcd.autotune(gauge, d, lqcd.F64, 1, ws1, stream=stream)
     torch.cuda.synchronize()
-
-    infos = []
 
     def step():
         out = []
@@ -138,53 +161,19 @@ def main():
             out.append(r.info[0])
         return out
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    value = 12 * args.steps / dt
+    dt, infos = timed(step, args.steps, args.warmup)
+    ms_step = dt * 1e3
+    value = 12 / dt
     rho_max = max(i["true_residual"] for i in infos)
     iters = [i["iters"] for i in infos]
     assert all(i["status"] == 0 for i in infos) and rho_max <= TOL, infos
-    log(f"FP64 eo-CG: {ms_step:.2f} ms / 12 solves, {value:.1f} solves/s, iters {iters}, "
-        f"max rho {rho_max:.2e}")
-
-    # ---- mixed precision, 12 rhs in one solve ---------------------------------
-    mixed = None
-    if not args.no_mixed:
-        mixed = {}
-        for name, ip in (("f32", lqcd.F32), ("bf16", lqcd.BF16)):
-            def mstep():
-                return lqcd.solve(gauge, eta, KAPPA, CSW, tol=TOL, solver=lqcd.SOLVER_CG_EO,
-                                  inner_prec=ip, reliable_every=100, use_graph=True, ws=ws12,
-                                  stream=stream, psi=psi, raise_on_noconv=False)
-            for _ in range(args.warmup):
-                mstep()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                r = mstep()
-            torch.cuda.synchronize()
-            mdt = time.perf_counter() - t0
-            ok = r.status == 0 and max(i["true_residual"] for i in r.info) <= TOL
-            sps = 12 * args.steps / mdt
-            mixed[name] = {"solves_per_s": round(sps, 2), "ms_per_12": round(mdt / args.steps * 1e3, 3),
-                           "vs_fp64": round(sps / value, 3), "converged": bool(ok),
-                           "iters": r.info[0]["iters"],
-                           "max_true_residual": max(i["true_residual"] for i in r.info),
-                           "reliable_updates": r.info[0]["reliable_updates"]}
-            log(f"mixed {name} 12-rhs: {mixed[name]}")
+    log(f"FP64 eo-CG 16^3x32: {ms_step:.2f} ms / 12 solves, {value:.1f} solves/s, iters {iters}, "
+        f"max rho {rho_max:.2e}, tuning {tune64}")
 
     # ---- roofline of the dominant kernel (FP64 odd->even hop + clover) -------
     vb = lqcd.vec_bytes(lat, lqcd.F64, 1, 2)
     vin = (torch.randn(vb // 8, device="cuda", dtype=torch.float64)).view(torch.uint8)
     vout = torch.empty(vb, dtype=torch.uint8, device="cuda")
-    d = lqcd.dirac(KAPPA, CSW)
 
     def hop_oe():
         lqcd.dw_apply_internal(gauge, d, vin, vout, lqcd.OP_HOP_OE, lqcd.F64, 1, ws1, stream=stream)
@@ -195,40 +184,46 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(DOMINANT_KERNEL),
                 "kernel": DOMINANT_KERNEL, "avg_launch_us": round(ms_oe * 1e3, 2),
-                "alg_bytes_per_launch": alg_bytes,
+                "alg_bytes_per_launch": alg_bytes, "tuning": tune64,
                 "note": "16^3x32 working set (~150 MB) fits the 256 MB last-level cache; "
                         "HBM-resident figures in dw_hbm"}
     log(f"roofline: {roofline}")
+    del vin, vout
 
-    # ---- Dw kernels at 32^3x64 (HBM-resident) ----------------------------------
-    dw_hbm = None
-    if not args.no_hbm:
-        del U
-        L3 = (32, 32, 32, 64)
-        U3 = inputs.gauge_field(L3, EPS, seed=3)
-        lat3 = lqcd.Lattice(L3, lqcd.BC_PERIODIC, THETA)
-        g3 = lqcd.GaugeField(lat3, torch.from_numpy(U3), pm, stream=stream)
-        del U3
-        ws3 = lqcd.Workspace(lat3, pm, 1)
-        d3 = lqcd.dirac(0.135, CSW)
-        dw_hbm = {"lattice": list(L3)}
-        for prec, pname in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.BF16, "bf16")):
-            vb3 = lqcd.vec_bytes(lat3, prec, 1, 2)
-            x3 = torch.randn(vb3 // 4, device="cuda").view(torch.uint8)
-            if prec == lqcd.BF16:  # finite bf16 pairs
-                x3 = torch.randn(vb3 // 2, device="cuda").to(torch.bfloat16).view(torch.uint8)
-            y3 = torch.empty(vb3, dtype=torch.uint8, device="cuda")
-            for op, oname, reals in ((lqcd.OP_HOP_EO, "hop_eo", REALS_HOP_EO),
-                                     (lqcd.OP_HOP_OE, "hop_oe", REALS_HOP_OE)):
-                f = (lambda op=op, prec=prec, x3=x3, y3=y3:
-                     lqcd.dw_apply_internal(g3, d3, x3, y3, op, prec, 1, ws3, stream=stream))
-                ms = time_launches(f, 50, stream)
-                gbs = reals * BYTES_PER_REAL[prec] * lat3.volume / (ms * 1e-3) / 1e9
-                dw_hbm[f"{oname}_{pname}"] = {"us": round(ms * 1e3, 1), "GB/s": round(gbs, 1),
-                                             "frac": round(gbs / HBM_PEAK_GBS, 4)}
-        log(f"dw_hbm: {dw_hbm}")
-        del g3, ws3
+    # ---- mixed precision, 12 rhs in one solve ---------------------------------
+    def mixed_leg(g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag):
+        res = {}
+        for name, ip in (("f32", lqcd.F32), ("bf16", lqcd.BF16)):
+            tune, _ = lqcd.autotune(g, lqcd.dirac(kappa, csw), ip, 12, ws, stream=stream)
+
+            def mstep():
+                return lqcd.solve(g, etas, kappa, csw, tol=TOL, solver=lqcd.SOLVER_CG_EO, inner_prec=ip,
+                                  reliable_every=100, use_graph=True, ws=ws, stream=stream,
+                                  raise_on_noconv=False)
+            mdt, r = timed(mstep, steps, warmup)
+            rho = max(i["true_residual"] for i in r.info)
+            sps = 12 / mdt
+            res[name] = {"solves_per_s": round(sps, 2), "ms_per_12": round(mdt * 1e3, 2),
+                         "vs_fp64": round(sps / fp64_sps, 3), "converged": bool(r.status == 0 and rho <= TOL),
+                         "iters": max(i["iters"] for i in r.info), "max_true_residual": rho,
+                         "reliable_updates": max(i["reliable_updates"] for i in r.info), "tuning": tune}
+            log(f"mixed {tag} {name} 12-rhs: {res[name]}")
+        return res
+
+    mixed = mixed_c4 = c3 = dw_hbm = serving = None
+    if not args.no_mixed:
+        mixed = mixed_leg(gauge, lat, ws12, eta, KAPPA, CSW, value, args.steps, args.warmup, "16^3x32")
+        del ws12
         torch.cuda.empty_cache()
+        mixed_c4 = c4_leg(stream, pm, mixed_leg, max(2, args.steps // 3))
+
+    # ---- 32^3x64: Z2 solve in three precisions and the kernels' HBM rates ----
+    if not args.no_hbm:
+        c3, dw_hbm = c3_leg(stream, pm, args.no_mixed)
+
+    # ---- serving -------------------------------------------------------------
+    if not args.no_serve:
+        serving = serve_leg(args.serve_requests, args.serve_rate, U2)
 
     # ---- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
@@ -246,15 +241,167 @@ def main():
                    "lattice": list(L_C2), "kappa": KAPPA, "csw": CSW, "bc": "periodic/antiperiodic",
                    "link_eps": EPS, "sources": 12, "tol": TOL, "solver": "eo-CG FP64, hipGraph chunks"},
         "iters_per_solve": iters, "max_true_residual": rho_max,
-        "roofline": roofline, "mixed": mixed, "dw_hbm": dw_hbm, "cpu_baseline": cpu,
+        "roofline": roofline, "mixed": mixed, "mixed_c4": mixed_c4, "c3": c3, "dw_hbm": dw_hbm,
+        "serving": serving, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def c4_leg(stream, pm, mixed_leg, steps):
+    """24^3x48 SF propagator: FP64 one source at a time vs mixed multi-RHS."""
+    import torch
+
+    from paper_2503_16994_amd import inputs, lqcd
+    L4 = (24, 24, 24, 48)
+    kappa, csw = 0.134, 1.8
+    U4 = inputs.gauge_field(L4, EPS, seed=4, bc=lqcd.BC_SF)
+    lat4 = lqcd.Lattice(L4, lqcd.BC_SF, (1, 1, 1, 1))
+    g4 = lqcd.GaugeField(lat4, torch.from_numpy(U4), pm, stream=stream)
+    del U4
+    eta4 = torch.from_numpy(inputs.point_sources_12(L4, (0, 0, 0, 1))).cuda()
+    ws1 = lqcd.Workspace(lat4, pm, 1)
+    lqcd.autotune(g4, lqcd.dirac(kappa, csw), lqcd.F64, 1, ws1, stream=stream)
+
+    def fstep():
+        return [lqcd.solve(g4, eta4[j:j + 1], kappa, csw, tol=TOL, inner_prec=lqcd.F64, use_graph=True,
+                           ws=ws1, stream=stream).info[0] for j in range(12)]
+    dt, infos = timed(fstep, steps, 1)
+    fp64 = 12 / dt
+    out = {"lattice": list(L4), "bc": "SF", "kappa": kappa, "csw": csw, "sources": "12 point at t=1",
+           "fp64_one_at_a_time": {"solves_per_s": round(fp64, 2), "ms_per_12": round(dt * 1e3, 2),
+                                  "iters": max(i["iters"] for i in infos),
+                                  "max_true_residual": max(i["true_residual"] for i in infos)}}
+    log(f"C4 FP64: {out['fp64_one_at_a_time']}")
+    del ws1
+    torch.cuda.empty_cache()
+    ws12 = lqcd.Workspace(lat4, pm, 12)
+    out.update(mixed_leg(g4, lat4, ws12, eta4, kappa, csw, fp64, steps, 1, "24^3x48 SF"))
+    del ws12, g4
+    torch.cuda.empty_cache()
+    return out
+
+
+def c3_leg(stream, pm, no_mixed):
+    """32^3x64: Z2-noise solve in FP64/FP32/BF16 and the hop kernels' HBM rates."""
+    import torch
+
+    from paper_2503_16994_amd import inputs, lqcd
+    L3 = (32, 32, 32, 64)
+    kappa = 0.135
+    U3 = inputs.gauge_field(L3, EPS, seed=3)
+    lat3 = lqcd.Lattice(L3, lqcd.BC_PERIODIC, THETA)
+    g3 = lqcd.GaugeField(lat3, torch.from_numpy(U3), pm, stream=stream)
+    del U3
+    ws3 = lqcd.Workspace(lat3, pm, 1)
+    d3 = lqcd.dirac(kappa, CSW)
+    dw_hbm = {"lattice": list(L3)}
+    for prec, pname in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.BF16, "bf16")):
+        tune, _ = lqcd.autotune(g3, d3, prec, 1, ws3, stream=stream)
+        vb3 = lqcd.vec_bytes(lat3, prec, 1, 2)
+        if prec == lqcd.BF16:  # finite bf16 pairs
+            x3 = torch.randn(vb3 // 2, device="cuda").to(torch.bfloat16).view(torch.uint8)
+        else:
+            x3 = torch.randn(vb3 // 4, device="cuda").view(torch.uint8)
+        y3 = torch.empty(vb3, dtype=torch.uint8, device="cuda")
+        for op, oname, reals in ((lqcd.OP_HOP_EO, "hop_eo", REALS_HOP_EO), (lqcd.OP_HOP_OE, "hop_oe", REALS_HOP_OE)):
+            f = (lambda op=op, prec=prec, x3=x3, y3=y3:
+                 lqcd.dw_apply_internal(g3, d3, x3, y3, op, prec, 1, ws3, stream=stream))
+            ms = time_launches(f, 50, stream)
+            gbs = reals * BYTES_PER_REAL[prec] * lat3.volume / (ms * 1e-3) / 1e9
+            dw_hbm[f"{oname}_{pname}"] = {"us": round(ms * 1e3, 1), "GB/s": round(gbs, 1),
+                                         "frac": round(gbs / HBM_PEAK_GBS, 4), "tuning": tune}
+        del x3, y3
+    log(f"dw_hbm: {dw_hbm}")
+    c3 = {"lattice": list(L3), "kappa": kappa, "csw": CSW, "source": "Z2 complex noise"}
+    eta3 = torch.from_numpy(inputs.z2_noise(L3, seed=3)).cuda()
+    precs = ((lqcd.F64, "f64"),) if no_mixed else ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.BF16, "bf16"))
+    for ip, name in precs:
+        def s3():
+            return lqcd.solve(g3, eta3, kappa, CSW, tol=TOL, inner_prec=ip, reliable_every=100, use_graph=True,
+                              ws=ws3, stream=stream, raise_on_noconv=False)
+        dt, r = timed(s3, 2, 1)
+        c3[name] = {"seconds": round(dt, 4), "iters": r.info[0]["iters"],
+                    "reliable_updates": r.info[0]["reliable_updates"],
+                    "true_residual": r.info[0]["true_residual"], "status": r.status}
+        if name != "f64":
+            c3[name]["vs_fp64"] = round(c3["f64"]["seconds"] / dt, 3)
+    log(f"C3: {c3}")
+    del ws3, g3, eta3
+    torch.cuda.empty_cache()
+    return c3, dw_hbm
+
+
+def serve_leg(n_requests, rate, U16):
+    """Poisson stream of propagator requests through lqcd_submit/lqcd_poll:
+    lattices {8^4, 16^3x32, 24^3x48, 32^3x64} x {open, periodic}, kappa uniform
+    in [0.125, 0.136], csw 1.9, 1 or 12 point sources, FP32 inner precision,
+    gauge fields resident.  Latency = completion - submission (server clock);
+    requests are submitted at their arrival times."""
+    import numpy as np
+
+    from paper_2503_16994_amd import inputs, lqcd
+    lats = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+    pm = lqcd.PM_F64 | lqcd.PM_F32
+    srv = lqcd.Server(200 << 30, max_streams=4)
+    gids = {}
+    etas = {}
+    for i, L in enumerate(lats):
+        U = U16 if L == L_C2 else inputs.gauge_field(L, EPS, seed=50 + i)
+        gids[(L, lqcd.BC_PERIODIC)] = srv.add_gauge(L, lqcd.BC_PERIODIC, THETA, U, pm)
+        gids[(L, lqcd.BC_OPEN)] = srv.add_gauge(L, lqcd.BC_OPEN, (1, 1, 1, 1), U, pm)
+        del U
+        src = inputs.point_sources_12(L, (0, 0, 0, 0))
+        etas[(L, 12)] = (src, np.empty_like(src))
+        etas[(L, 1)] = (src[:1].copy(), np.empty_like(src[:1]))
+    rng = np.random.Generator(np.random.PCG64(99))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    reqs = []
+    for k in range(n_requests):
+        L = lats[int(rng.integers(0, 4))]
+        bc = lqcd.BC_OPEN if rng.integers(0, 2) else lqcd.BC_PERIODIC
+        kappa = float(rng.uniform(0.125, 0.136))
+        nrhs = 12 if rng.integers(0, 2) else 1
+        reqs.append((L, bc, kappa, nrhs))
+    t0 = time.perf_counter()
+    arrival = np.cumsum(gaps)
+    tickets = []
+    for k, (L, bc, kappa, nrhs) in enumerate(reqs):
+        wait = arrival[k] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        p = lqcd.Server.params(kappa, 1.9, tol=TOL, inner_prec=lqcd.F32, nrhs=nrhs)
+        e, ps = etas[(L, nrhs)]
+        tickets.append(srv.submit(gids[(L, bc)], p, e, ps))
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    lat_s = np.array([done[t][2][2] - done[t][2][0] for t in tickets])
+    wait_s = np.array([done[t][2][1] - done[t][2][0] for t in tickets])
+    ok = sum(1 for t in tickets if done[t][0] == lqcd.OK)
+    nsolves = sum(r[3] for r in reqs)
+    peak = srv.peak_bytes()
+    srv.close()
+    out = {"requests": n_requests, "rate_per_s": rate, "ok": ok, "solves": int(nsolves),
+           "p50_latency_s": round(float(np.percentile(lat_s, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat_s, 99)), 4),
+           "mean_admission_wait_s": round(float(wait_s.mean()), 4),
+           "solves_per_s": round(nsolves / wall, 2), "requests_per_s": round(n_requests / wall, 3),
+           "wall_s": round(wall, 3), "peak_arena_gib": round(peak / 2**30, 2),
+           "note": "offered load is far above capacity, so latencies measure the backlog"}
+    log(f"serving: {out}")
+    return out
 
 
 def profile_kernels(stream):
     """Launch sequence for rocprofv3 counter runs: a plain 1 GiB device copy
     (to calibrate FETCH_SIZE/WRITE_SIZE against known bytes), then 20 launches
-    of each hop kernel in FP64 at 16^3x32 and at 32^3x64."""
+    of each hop kernel in FP64 at 16^3x32 and at 32^3x64 (default tuning)."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -287,8 +434,6 @@ def profile_kernels(stream):
 
 def cpu_baseline():
     """Oracle (plain FP64 full-lattice CG, OpenMP over sites) on the host."""
-    import numpy as np
-
     from oracle import oracle as orc
     from paper_2503_16994_amd import inputs
 

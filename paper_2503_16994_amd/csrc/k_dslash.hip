@@ -157,44 +157,50 @@ __device__ inline double block_sum_rl(double v, double* sh) {
   return s;
 }
 
-template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL>
-__global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
-  using A = typename StoreTraits<SG>::acc;
+// Everything a hop launch computes for one thread before the output stage:
+// block decode, the 8 hops, the clover blocks.  Leaves the NR output
+// spinors in v (scaled hop sum plus pre(z), then post), and the site, its
+// coordinates and the rhs indices in the outputs.
+struct ThreadSite {
+  int sb, rhs_tile0, rhs0, s, p;
+  bool active, masked;
+};
+
+template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL, typename A>
+__device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v)[NR][12]) {
   constexpr int SPB = kHopBlock / RL;  // sites per block
-  __shared__ double red[(kHopBlock / 64) * RL];
   const KGeom& g = a.g;
-  // decode (site block, rhs tile) from the 1-D grid; see block_order()
-  int sb, tile;
-  block_order(a, blockIdx.x, gridDim.x, a.nrhs / (NR * RL), sb, tile);
+  int tile;
+  block_order(a, blockIdx.x, gridDim.x, a.nrhs / (NR * RL), ts.sb, tile);
   const int lane_r = (RL > 1) ? (int)(threadIdx.x % RL) : 0;
-  const int rhs_tile0 = tile * NR * RL;
-  const int rhs0 = rhs_tile0 + lane_r * NR;  // this lane's first rhs
+  ts.rhs_tile0 = tile * NR * RL;
+  ts.rhs0 = ts.rhs_tile0 + lane_r * NR;  // this lane's first rhs
   if (a.done) {
     bool all = true;
     for (int r = 0; r < NR * RL; ++r)
-      all = all && (a.done[(rhs_tile0 + r) * (int)(sizeof(CGState) / sizeof(int))] != 0);
-    if (all) return;
+      all = all && (a.done[(ts.rhs_tile0 + r) * (int)(sizeof(CGState) / sizeof(int))] != 0);
+    if (all) return false;
   }
-  // parity of this block's output sites and its site index
-  int p = a.p_out, bx = sb;
+  int p = a.p_out, bx = ts.sb;
   if (a.both) {
     const int nbh = a.nbs >> 1;
     p = (bx >= nbh) ? 1 : 0;
     bx -= p * nbh;
   }
+  ts.p = p;
   const int s = bx * SPB + (int)(threadIdx.x / RL);
-  const bool active = s < g.V2;
+  ts.s = s;
+  ts.active = s < g.V2;
   const size_t V2 = (size_t)g.V2;
   const SI* yb = static_cast<const SI*>(a.y);
   const SI* zb = static_cast<const SI*>(a.z);
-  SO* ob = static_cast<SO*>(a.out);
   const SG* cpre = static_cast<const SG*>(a.Cpre);
   if (a.both) {
     yb += (1 - p) * a.par_stride;
     if (zb) zb += p * a.par_stride;
-    ob += p * a.par_stride;
     if (cpre) cpre += p * a.cpre_par;
   }
+  const int rhs0 = ts.rhs0;
 
   cpx<A> acc[NR][4][3];
 #pragma unroll
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
 
   Coord c;
   c.t = 0;
-  if (active) {
+  if (ts.active) {
     c = site_coord(g, s, p);
     if (HOP) {
       hop_dir<0, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
@@ -219,17 +225,14 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
       hop_dir<3, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
     }
   }
-  const bool masked = (g.bc == BC_SF) && (c.t == 0);
+  ts.masked = (g.bc == BC_SF) && (c.t == 0);
   const A scale = (A)a.scale;
 
-  // v[r] = scale * H y  (+ pre(z)), then post; the clover blocks are loaded
-  // one chirality at a time and applied to all NR rhs of the thread
-  cpx<A> v[NR][12];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[r][k] = cscale(scale, acc[r][k / 3][k % 3]);
-  if (active && PRE != PRE_NONE) {
+  if (ts.active && PRE != PRE_NONE) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Cm[18];
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
       }
     }
   }
-  if (active && POST == POST_CLOV) {
+  if (ts.active && POST == POST_CLOV) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Ci[18];
@@ -271,20 +274,35 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
       }
     }
   }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (a.g5) {
+#pragma unroll
+      for (int k = 6; k < 12; ++k) v[r][k] = {-v[r][k].re, -v[r][k].im};
+    }
+    if (ts.masked) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[r][k] = {(A)0, (A)0};
+    }
+  }
+  return true;
+}
 
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL>
+__global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
+  using A = typename StoreTraits<SG>::acc;
+  __shared__ double red[(kHopBlock / 64) * RL];
+  ThreadSite ts;
+  cpx<A> v[NR][12];
+  if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL>(a, ts, v)) return;
+  const size_t V2 = (size_t)a.g.V2;
+  SO* ob = static_cast<SO*>(a.out);
+  if (a.both) ob += ts.p * a.par_stride;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     double nrm = 0.0;
-    if (active) {
-      if (a.g5) {
-#pragma unroll
-        for (int k = 6; k < 12; ++k) v[r][k] = {-v[r][k].re, -v[r][k].im};
-      }
-      if (masked) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) v[r][k] = {(A)0, (A)0};
-      }
-      SO* op = ob + (size_t)(rhs0 + r) * a.out_rs + s;
+    if (ts.active) {
+      SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + ts.s;
 #pragma unroll
       for (int k = 0; k < 12; ++k) st(op + k * V2, v[r][k]);
       if (a.partials) {
@@ -296,8 +314,53 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
     if (a.partials) {
       const double bs = block_sum_rl<RL>(nrm, red);
       if ((int)threadIdx.x < RL)
-        a.partials[(size_t)(rhs_tile0 + (int)threadIdx.x * NR + r) * a.nbs + sb] = bs;
+        a.partials[(size_t)(ts.rhs_tile0 + (int)threadIdx.x * NR + r) * a.nbs + ts.sb] = bs;
     }
+  }
+}
+
+// The last hop of a CG iteration fused with the vector update: with
+// Ap = g5 (A_ee q + 1/2 H t) computed in registers, every rhs that is not done
+// gets x += alpha p, r -= alpha Ap (x, r, p of type SV at this site) and the
+// per-block |r|^2 partial.  Ap is never stored.
+template <typename SG, typename SI, typename SV, int NR, int RL>
+__global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
+  using A = typename StoreTraits<SG>::acc;
+  using AV = typename StoreTraits<SV>::acc;
+  __shared__ double red[(kHopBlock / 64) * RL];
+  ThreadSite ts;
+  cpx<A> v[NR][12];
+  if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL>(a, ts, v)) return;
+  const size_t V2 = (size_t)a.g.V2;
+  SV* xb = static_cast<SV*>(a.xr_x);
+  SV* rb = static_cast<SV*>(a.xr_r);
+  const SV* pb = static_cast<const SV*>(a.xr_p);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int q = ts.rhs0 + r;
+    const CGState& cs = a.cg[q];
+    double nrm = 0.0;
+    if (ts.active && !cs.done) {
+      const double alpha_d = cs.alpha;
+      const AV alpha = (AV)alpha_d;
+      const size_t o = (size_t)q * a.xr_rs + ts.s, ox = (size_t)q * a.xr_xrs + ts.s;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        auto pv = ld(pb + o + k * V2);
+        auto xv = ld(xb + ox + k * V2);
+        auto rv = ld(rb + o + k * V2);
+        xv.re += (AV)alpha_d * pv.re;
+        xv.im += (AV)alpha_d * pv.im;
+        rv.re -= alpha * (AV)v[r][k].re;
+        rv.im -= alpha * (AV)v[r][k].im;
+        st(xb + ox + k * V2, xv);
+        st(rb + o + k * V2, rv);
+        nrm += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+      }
+    }
+    const double bs = block_sum_rl<RL>(nrm, red);
+    if ((int)threadIdx.x < RL)
+      a.partials[(size_t)(ts.rhs_tile0 + (int)threadIdx.x * NR + r) * a.nbs + ts.sb] = bs;
   }
 }
 
@@ -307,6 +370,13 @@ int hop_nblocks(const HopLaunch& h) {
   const int spb = sites_per_block(h.rhs_lanes);
   const int nb = (h.g.V2 + spb - 1) / spb;
   return h.both ? 2 * nb : nb;
+}
+
+// per-rhs partial sums a launch of the tiled shapes writes (its site blocks)
+int hop_nparts(const HopLaunch& h0) {
+  HopLaunch h = h0;
+  if (h.prec == P_F64) h.rhs_lanes = 1;
+  return hop_nblocks(h);
 }
 
 // fill in nbs/bpp and validate the block order for this launch
@@ -354,6 +424,48 @@ static hipError_t launch_tiled(const HopLaunch& h0, hipStream_t st) {
       default: return hipErrorInvalidValue;
     }
   }
+}
+
+template <typename SG, typename SI, typename SV, int RL>
+static hipError_t launch_xr_rl(const HopLaunch& h, hipStream_t st) {
+  const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
+  switch (h.nr_tile) {
+    case 1: k_hop_xr<SG, SI, SV, 1, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 2: k_hop_xr<SG, SI, SV, 2, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 3: k_hop_xr<SG, SI, SV, 3, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 4: k_hop_xr<SG, SI, SV, 4, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename SG, typename SI, typename SV>
+static hipError_t launch_xr(const HopLaunch& h0, hipStream_t st) {
+  HopLaunch h = h0;
+  if (std::is_same<SG, double2>::value) h.rhs_lanes = 1;
+  if (!prepare(h) || h.both || !h.partials || !h.cg) return hipErrorInvalidValue;
+  if constexpr (std::is_same<SG, double2>::value) {
+    return launch_xr_rl<SG, SI, SV, 1>(h, st);
+  } else {
+    switch (h.rhs_lanes) {
+      case 1: return launch_xr_rl<SG, SI, SV, 1>(h, st);
+      case 2: return launch_xr_rl<SG, SI, SV, 2>(h, st);
+      case 4: return launch_xr_rl<SG, SI, SV, 4>(h, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+hipError_t launch_hop_xr(const HopLaunch& h, hipStream_t st) {
+  if (h.g.V2 <= 0 || h.nrhs <= 0 || !h.hop || h.pre != PRE_CLOV || h.post != POST_NONE)
+    return hipErrorInvalidValue;
+  if (h.prec == P_F64 && h.in_prec == P_F64 && h.xr_prec == P_F64)
+    return launch_xr<double2, double2, double2>(h, st);
+  if (h.prec == P_F32 && h.in_prec == P_F32 && h.xr_prec == P_F32)
+    return launch_xr<float2, float2, float2>(h, st);
+  if (h.prec == P_BF16 && h.in_prec == P_BF16 && h.xr_prec == P_F32)
+    return launch_xr<bf16x2, bf16x2, float2>(h, st);
+  return hipErrorInvalidValue;
 }
 
 // set-up shapes (source preparation, reconstruction, block application):

@@ -211,7 +211,7 @@ WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base) {
     m.qb = (bf16x2*)take(half16);
     m.tb = (bf16x2*)take(half16);
   }
-  const int hop_parts = 2 * (int)((V2 + 255) / 256);
+  const int hop_parts = 2 * (int)((V2 + 63) / 64);  // up to 4 rhs lanes per site
   m.max_parts = hop_parts > 2048 ? hop_parts : 2048;
   m.partials = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
   m.partials2 = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));

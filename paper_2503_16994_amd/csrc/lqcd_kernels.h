@@ -58,10 +58,21 @@ struct HopLaunch {
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
   int bpp;  // site blocks per (z, t) plane
+  // fused CG update (launch_hop_xr): x += alpha p, r -= alpha out for every
+  // rhs not done, |r|^2 partials into `partials`; out itself is not stored
+  void* xr_x;
+  void* xr_r;
+  const void* xr_p;
+  int xr_prec;   // precision of x, r, p
+  long xr_rs;    // rhs stride of r and p
+  long xr_xrs;   // rhs stride of x
+  const struct CGState* cg;
 };
 
 int hop_nblocks(const HopLaunch& h);
+int hop_nparts(const HopLaunch& h);  // partials per rhs of a tiled hop launch
 hipError_t launch_hop(const HopLaunch& h, hipStream_t st);
+hipError_t launch_hop_xr(const HopLaunch& h, hipStream_t st);
 
 // Gauge import: canonical complex128 U -> internal links (any non-null
 // precision pointer is written); OPEN zeroes U_t(T-1).

@@ -127,6 +127,39 @@ hipError_t hop_oe(const Ctl& c, int lprec, Vec z, Vec t_o, Vec out, bool g5, dou
   return launch_hop(h, c.st);
 }
 
+// fused last hop + CG update: Ap = g5 (A_ee q_e + 1/2 H t_o) in registers,
+// x += alpha p, r -= alpha Ap, |r|^2 partials (x, r, p vectors of precision
+// vprec)
+hipError_t hop_oe_xr(const Ctl& c, int lprec, Vec q, Vec t_o, Vec x, Vec r, Vec p, double* partials,
+                     const CGState* cg, const int* done) {
+  HopLaunch h = mk(c, lprec);
+  h.p_out = 0;
+  h.in_prec = q.prec;
+  h.out_prec = r.prec;
+  h.y = t_o.p;
+  h.y_rs = t_o.rs;
+  h.z = q.p;
+  h.z_rs = q.rs;
+  h.Cpre = clov_of(c.w, lprec);
+  h.pre = PRE_CLOV;
+  h.post = POST_NONE;
+  h.scale = 0.5;
+  h.g5 = true;
+  h.partials = partials;
+  h.done = done;
+  h.xr_x = x.p;
+  h.xr_r = r.p;
+  h.xr_p = p.p;
+  h.xr_prec = r.prec;
+  h.xr_rs = r.rs;
+  h.xr_xrs = x.rs;
+  h.cg = cg;
+  return launch_hop_xr(h, c.st);
+}
+
+// partial sums per rhs that the tuned iteration hops of precision lprec write
+int iter_parts(const Ctl& c, int lprec) { return hop_nparts(mk(c, lprec)); }
+
 // out (full, both parities) = [g5] Dw y, optional partials
 hipError_t dw_full(const Ctl& c, const double2* y, double2* out, bool g5, double* partials,
                    const int* done) {
@@ -335,32 +368,34 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   };
 
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
+  // eo: hop, hop (+g5, |Dhat p|^2), alpha, hop, hop fused with the x/r update
+  // (+|r|^2), beta, [reliable-update group], p update
   constexpr int kRuStride = 5;
+  const int nb_it = eo ? iter_parts(c, lprec) : nb_op;
   auto iteration = [&](int i) -> hipError_t {
     hipError_t e;
     if (eo) {
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
+      if ((e = launch_cg_alpha(cg, parts, nb_it, N, st))) return e;
+      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile))) return e;
+      if ((e = hop_oe_xr(c, lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
+      if ((e = launch_cg_beta(cg, parts, nb_it, N, st))) return e;
     } else {
       if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
-    }
-    if ((e = launch_cg_alpha(cg, parts, nb_op, N, st))) return e;
-    if (eo) {
-      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile))) return e;
-      if ((e = hop_oe(c, lprec, qin, tin, api, true, nullptr, done, nr_tile))) return e;
-    } else {
+      if ((e = launch_cg_alpha(cg, parts, nb_op, N, st))) return e;
       if ((e = dw_full(c, (const double2*)qin.p, (double2*)api.p, true, nullptr, done))) return e;
+      if ((e = launch_cg_xr(xi.p, xi.prec, xi.rs, ri.p, pi.p, api.p, ri.prec, n_vec, ri.rs, N, cg, parts,
+                            st)))
+        return e;
+      if ((e = launch_cg_beta(cg, parts, nb_blas, N, st))) return e;
     }
-    if ((e = launch_cg_xr(xi.p, xi.prec, xi.rs, ri.p, pi.p, api.p, ri.prec, n_vec, ri.rs, N, cg, parts, st)))
-      return e;
-    if ((e = launch_cg_beta(cg, parts, nb_blas, N, st))) return e;
     if ((i + 1) % kRuStride == 0 && (e = reliable_update())) return e;
     if ((e = launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, lo16 ? pin.p : nullptr,
                          lo16 ? P_BF16 : P_F32, st)))
       return e;
     return hipSuccess;
   };
-
   constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
   const bool use_graph = prm->use_graph && st != nullptr;
   hipGraphExec_t exec = nullptr;

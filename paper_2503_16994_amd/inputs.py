@@ -24,6 +24,9 @@ not available here; these seeded fields stand in for them):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 PERIODIC, SF, OPEN = 0, 1, 2
@@ -58,12 +61,26 @@ def gauge_field(L, eps: float, seed: int, bc: int = PERIODIC, sf_phi=(0.0, 0.0),
     lam = _gell_mann() / 2.0
     U = np.empty((V * 4, 3, 3), np.complex128)
     n = V * 4
+    # the draws are sequential (reproducible); the exponentials of the chunks
+    # are independent and run on a thread pool (LAPACK releases the GIL)
+    chunks = []
     for s in range(0, n, chunk):
         m = min(chunk, n - s)
-        h = rng.standard_normal((m, 8))
+        chunks.append((s, m, rng.standard_normal((m, 8))))
+
+    def expo(item):
+        s, m, h = item
         H = np.einsum("na,aij->nij", h, lam)
         w, v = np.linalg.eigh(H)
         U[s:s + m] = np.einsum("nij,nj,nkj->nik", v, np.exp(1j * eps * w), v.conj())
+
+    workers = min(len(chunks), max(1, min(16, os.cpu_count() or 1)))
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(expo, chunks))
+    else:
+        for item in chunks:
+            expo(item)
     U = U.reshape(T, Lz, Ly, Lx, 4, 3, 3)
     if bc == SF:
         phi1, phi2 = sf_phi
