@@ -230,12 +230,22 @@ typedef struct lqcd_solve_info {
   int32_t status;           /* LQCD_OK or LQCD_ENOCONV for this rhs */
   int32_t iters;            /* CG iterations (applications of the normal op) */
   int32_t reliable_updates; /* FP64 residual recomputations */
-  int32_t restarts;
+  int32_t restarts;         /* tightenings of the inner target */
+  int32_t fp64_from;        /* mixed precision: iteration after which this rhs
+                               continued in FP64 because the low-precision
+                               recursion stopped reducing the true residual
+                               (0: never) */
+  int32_t reserved;
   double true_residual;     /* |eta - Dw psi|/|eta| recomputed in FP64 with the
                                full-lattice operator after the solve */
   double seconds;           /* wall time of the whole call */
 } lqcd_solve_info;
 
+/* Mixed precision (inner_prec FP32 or BF16): when eight consecutive reliable
+ * updates have not halved the best true residual of a rhs (the inner
+ * precision cannot resolve the system: its condition number times the unit
+ * roundoff is near one), that rhs continues as FP64 CG from its current
+ * solution (info.fp64_from).  The result still meets tol. */
 /* Solves Dw psi_j = eta_j for j < nrhs.  eta and psi are canonical
  * complex128 fields on the device (nrhs stacked).  With SF boundaries eta
  * must vanish on slice t = 0 (EINVAL otherwise).  Returns LQCD_OK if every

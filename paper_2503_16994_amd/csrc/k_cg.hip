@@ -9,11 +9,21 @@
 // pending request, so a captured graph contains them unconditionally.  The
 // update's finish kernel also performs the convergence test on the true
 // residual and marks the rhs done.  The host only polls the done flags.
+//
+// Stall detection.  A low-precision recursion on a system whose condition
+// number times the unit roundoff of the inner precision approaches one
+// (e.g. near-zero modes) makes little or no progress on the true residual
+// however long it runs.  Every reliable update compares the true residual
+// with the best one so far; after stall_max consecutive updates without
+// halving it the rhs is marked CG_STALLED and the host continues it in FP64
+// from the current solution.  Healthy solves gain about a factor ten per
+// update (the update is triggered by a tenfold drop of the recursive |r|).
 #include "lqcd_kernels.h"
 
 namespace lqcd {
 
 constexpr int kB = 256;
+constexpr double kGain2 = 0.25;  // required gain on |eta - Dw x|^2 (halving the residual)
 
 __device__ inline double bsum(double v, double* sh) {
 #pragma unroll
@@ -65,6 +75,12 @@ __global__ void k_cg_setup(CGState* s, const double* b2, const double* eta2, CGS
   c.ru_every = cfg.ru_every;
   c.last_ru = 0;
   c.skip_ru = 1;
+  c.target0 = c.target2;
+  c.no_gain = 0;
+  c.best_rho2 = 1.0;
+  c.stall_max = cfg.stall_max;
+  c.fp64_from = 0;
+  c.pad_ = 0;
   const bool zero = !(b > 0.0) || !(eta2[r] > 0.0);
   c.done = zero ? 1 : 0;
   c.status = zero ? CG_CONVERGED : CG_RUNNING;
@@ -231,6 +247,19 @@ __global__ void k_ru_finish(CGState* s, const double* part_res, int n_res, const
     c.status = CG_CONVERGED;
     return;
   }
+  if (c.stall_max > 0) {
+    if (c.rho2 < kGain2 * c.best_rho2) {
+      c.best_rho2 = c.rho2;
+      c.no_gain = 0;
+    } else {
+      c.no_gain += 1;
+    }
+    if (c.no_gain >= c.stall_max) {
+      c.done = 1;
+      c.status = CG_STALLED;
+      return;
+    }
+  }
   if (c.inner_hit) {  // inner target reached without the true one: tighten it
     c.target2 *= 0.01;
     c.restarts += 1;
@@ -245,7 +274,33 @@ __global__ void k_ru_finish(CGState* s, const double* part_res, int n_res, const
   }
 }
 
+__global__ void k_cg_escalate(CGState* s, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  CGState& c = s[r];
+  if (c.status != CG_STALLED) {
+    c.skip_ru = 1;
+    return;
+  }
+  c.done = 0;
+  c.status = CG_RUNNING;
+  c.skip_ru = 0;  // the first FP64 step recomputes r from x
+  c.stall_max = 0;
+  c.no_gain = 0;
+  c.delta2 = 0.0;
+  c.ru_every = 0;
+  c.inner_hit = 0;
+  c.target2 = c.target0;
+  c.alpha = 0.0;
+  c.beta = 0.0;  // p = r after the update
+  c.fp64_from = c.iters;
+}
+
 // ---------------------------------------------------------------------------
+hipError_t launch_cg_escalate(CGState* s, int nrhs, hipStream_t st) {
+  k_cg_escalate<<<(nrhs + 63) / 64, 64, 0, st>>>(s, nrhs);
+  return hipGetLastError();
+}
 hipError_t launch_cg_setup(CGState* s, const double* b2, const double* eta2, const CGSetup& cfg,
                            hipStream_t st) {
   k_cg_setup<<<(cfg.nrhs + 63) / 64, 64, 0, st>>>(s, b2, eta2, cfg);

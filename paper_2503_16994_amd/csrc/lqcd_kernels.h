@@ -103,7 +103,9 @@ struct CloverLaunch {
 hipError_t launch_clover(const CloverLaunch& c, hipStream_t st);
 
 // ---- vector algebra on flat arrays of n complex elements per rhs -----------
-enum CGStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_NONFINITE = 3 };
+// CG_STALLED: the low-precision recursion no longer tracks the true residual
+// (see k_ru_finish); the rhs continues in FP64 after launch_cg_escalate.
+enum CGStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_NONFINITE = 3, CG_STALLED = 4 };
 
 // CG control of one right-hand side (device memory)
 struct CGState {
@@ -128,6 +130,12 @@ struct CGState {
   int inner_hit;
   int ru_every;    // reliable update at least every ru_every iterations (0: off)
   int last_ru;     // iteration of the last reliable update
+  double target0;    // initial inner target
+  double best_rho2;  // smallest true residual^2 (relative) at a reliable update
+  int no_gain;       // consecutive reliable updates that did not halve best_rho2
+  int stall_max;     // CG_STALLED after this many (0: never)
+  int fp64_from;     // iteration at which the rhs continued in FP64 (0: never)
+  int pad_;
 };
 
 struct CGSetup {
@@ -137,6 +145,7 @@ struct CGSetup {
   double inner_rel;  // initial inner target relative to |b|
   double delta2;
   int ru_every;
+  int stall_max;
 };
 
 int blas_nblocks(long n);
@@ -165,6 +174,10 @@ hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long
                           const CGState* s, hipStream_t st);
 hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r,
                             int n_r, int nrhs, hipStream_t st);
+// every CG_STALLED rhs becomes a running FP64 rhs with a pending reliable
+// update (which recomputes r from x); every other rhs keeps its state and has
+// no pending update
+hipError_t launch_cg_escalate(CGState* s, int nrhs, hipStream_t st);
 
 // y = a*x + b*y  (element types by precision), per-rhs scalars not needed
 hipError_t launch_axpby(double a, const void* x, int xprec, double b, void* y, int yprec,

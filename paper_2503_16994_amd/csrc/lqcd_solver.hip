@@ -312,31 +312,38 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   }
   LQCD_HIP(launch_reduce(parts, nb_op, N, scal, st));
 
-  // inner operands
-  const bool lo16 = (ip == LQCD_BF16);  // BF16 storage of the operator's operands
+  // inner operands of a phase: the low-precision recursion (mixed solves) or
+  // FP64 (plain solves, and the continuation of stalled mixed rhs)
+  bool lo = false, lo16 = false;  // phase in low precision; BF16 operator operands
   Vec xi, ri, pi, qi, api, ti, pin, qin, tin;
-  long n_vec;  // complex elements per rhs of one inner vector
+  const long n_vec = eo ? 12 * V2 : 24 * V2;  // complex elements per rhs of one inner vector
+  int lprec = P_F64, nb_blas = blas_nblocks(n_vec);
+  auto select = [&](bool low) {
+    lo = low;
+    lo16 = low && ip == LQCD_BF16;
+    lprec = low ? ip : P_F64;
+    if (!low) {
+      xi = X; ri = R; pi = P; qi = Q; api = AP; ti = odd_part(TMP, V2);
+      pin = pi; qin = qi; tin = ti;
+    } else {
+      xi = Vec{m.xl, P_F32, HRS}; ri = Vec{m.rl, P_F32, HRS}; pi = Vec{m.pl, P_F32, HRS};
+      qi = Vec{m.ql, P_F32, HRS}; api = Vec{m.apl, P_F32, HRS}; ti = Vec{m.tl, P_F32, HRS};
+      if (lo16) {
+        pin = Vec{m.pb, P_BF16, HRS}; qin = Vec{m.qb, P_BF16, HRS}; tin = Vec{m.tb, P_BF16, HRS};
+      } else {
+        pin = pi; qin = qi; tin = ti;
+      }
+    }
+  };
+  select(mixed);
   if (!mixed) {
-    xi = X; ri = R; pi = P; qi = Q; api = AP; ti = odd_part(TMP, V2);
-    pin = pi; qin = qi; tin = ti;
-    n_vec = eo ? 12 * V2 : 24 * V2;
     LQCD_HIP(hipMemcpyAsync(m.P, m.R, full_bytes, hipMemcpyDeviceToDevice, st));
   } else {
-    xi = Vec{m.xl, P_F32, HRS}; ri = Vec{m.rl, P_F32, HRS}; pi = Vec{m.pl, P_F32, HRS};
-    qi = Vec{m.ql, P_F32, HRS}; api = Vec{m.apl, P_F32, HRS}; ti = Vec{m.tl, P_F32, HRS};
-    n_vec = 12 * V2;
-    if (lo16) {
-      pin = Vec{m.pb, P_BF16, HRS}; qin = Vec{m.qb, P_BF16, HRS}; tin = Vec{m.tb, P_BF16, HRS};
-    } else {
-      pin = pi; qin = qi; tin = ti;
-    }
     LQCD_HIP(launch_fill_zero(m.xl, (size_t)N * HRS * 8, st));
     LQCD_HIP(launch_convert(m.R, P_F64, m.rl, P_F32, n_vec, FRS, HRS, N, st));
     LQCD_HIP(launch_convert(m.rl, P_F32, m.pl, P_F32, n_vec, HRS, HRS, N, st));
     if (lo16) LQCD_HIP(launch_convert(m.rl, P_F32, m.pb, P_BF16, n_vec, HRS, HRS, N, st));
   }
-  const int lprec = mixed ? ip : P_F64;
-  const int nb_blas = blas_nblocks(n_vec);
   const int nr_tile = 0;  // 0: the workspace's tuned tile
 
   CGSetup cfg;
@@ -346,19 +353,20 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   cfg.inner_rel = 0.1 * tol;
   cfg.delta2 = mixed ? 0.01 : 0.0;
   cfg.ru_every = mixed ? (prm->reliable_every > 0 ? prm->reliable_every : 100) : 0;
+  cfg.stall_max = mixed ? 8 : 0;
   LQCD_HIP(launch_cg_setup(cg, scal, scal + N, cfg, st));
 
   // ---- reliable update group (skips rhs without a pending request) ---------
   auto reliable_update = [&]() -> hipError_t {
     hipError_t e;
     if (eo) {
-      if (mixed && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
+      if (lo && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
       if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, 1))) return e;
       if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, 1))) return e;
       if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, V2, N, cg, parts2, st))) return e;
       if ((e = hop_eo(c, P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
-      if ((e = hop_oe(c, P_F64, AP, odd_part(TMP, V2), mixed ? Q : R, true, parts, skip_ru, 1))) return e;
-      if (mixed && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
+      if ((e = hop_oe(c, P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, 1))) return e;
+      if (lo && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
       return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_hop, N, st);
     }
     if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
@@ -371,10 +379,10 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   // eo: hop, hop (+g5, |Dhat p|^2), alpha, hop, hop fused with the x/r update
   // (+|r|^2), beta, [reliable-update group], p update
   constexpr int kRuStride = 5;
-  const int nb_it = eo ? iter_parts(c, lprec) : nb_op;
   auto iteration = [&](int i) -> hipError_t {
     hipError_t e;
     if (eo) {
+      const int nb_it = iter_parts(c, lprec);
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
       if ((e = launch_cg_alpha(cg, parts, nb_it, N, st))) return e;
@@ -398,15 +406,16 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   };
   constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
   const bool use_graph = prm->use_graph && st != nullptr;
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    for (auto& e : w->graphs)
-      if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == ip && e.nrhs == N &&
-          e.chunk == K)
-        exec = e.exec;
-  }
+  // a chunk of K iterations, replayed from a graph cached in the workspace
+  // (keyed by everything the captured launches depend on)
   auto run_chunk = [&]() -> int {
     if (use_graph) {
+      const int key_prec = lo ? ip : LQCD_F64;
+      hipGraphExec_t exec = nullptr;
+      for (auto& e : w->graphs)
+        if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == key_prec && e.nrhs == N &&
+            e.chunk == K)
+          exec = e.exec;
       if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
@@ -423,7 +432,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
           (void)hipGraphDestroy(gr);
           return hip_status(e3, "hipGraphInstantiate");
         }
-        w->graphs.push_back(GraphEntry{u->uid, prm->solver, ip, N, K, gr, exec});
+        w->graphs.push_back(GraphEntry{u->uid, prm->solver, key_prec, N, K, gr, exec});
       }
       LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;
@@ -435,20 +444,43 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   std::vector<CGState> hs(N);
   const bool trace = getenv("LQCD_TRACE") != nullptr;  // per-chunk progress on stderr
   const long max_chunks = (long)prm->maxiter / K + 3;
-  for (long chunk = 0;; ++chunk) {
-    rc = run_chunk();
-    if (rc) return rc;
-    LQCD_HIP(hipMemcpyAsync(hs.data(), cg, sizeof(CGState) * N, hipMemcpyDeviceToHost, st));
-    LQCD_HIP(hipStreamSynchronize(st));
-    bool all_done = true;
-    for (int r = 0; r < N; ++r) {
-      all_done = all_done && hs[r].done;
-      if (trace)
-        fprintf(stderr, "[lqcd] rhs %d iters %d done %d status %d rr/b2 %.3e rho %.3e rupd %d\n", r,
-                hs[r].iters, hs[r].done, hs[r].status, hs[r].rr / hs[r].bnorm2, sqrt(hs[r].rho2),
-                hs[r].rupd);
+  long chunk = 0;
+  // runs chunks until every rhs is done; returns whether one is CG_STALLED
+  auto run_phase = [&](bool& stalled) -> int {
+    stalled = false;
+    for (;; ++chunk) {
+      int rc2 = run_chunk();
+      if (rc2) return rc2;
+      LQCD_HIP(hipMemcpyAsync(hs.data(), cg, sizeof(CGState) * N, hipMemcpyDeviceToHost, st));
+      LQCD_HIP(hipStreamSynchronize(st));
+      bool all_done = true;
+      stalled = false;
+      for (int r = 0; r < N; ++r) {
+        all_done = all_done && hs[r].done;
+        stalled = stalled || hs[r].status == CG_STALLED;
+        if (trace)
+          fprintf(stderr, "[lqcd] rhs %d iters %d done %d status %d rr/b2 %.3e rho %.3e rupd %d%s\n", r,
+                  hs[r].iters, hs[r].done, hs[r].status, hs[r].rr / hs[r].bnorm2, sqrt(hs[r].rho2),
+                  hs[r].rupd, lo ? "" : " fp64");
+      }
+      if (all_done || chunk >= max_chunks) return LQCD_OK;
     }
-    if (all_done || chunk >= max_chunks) break;
+  };
+  bool stalled = false;
+  rc = run_phase(stalled);
+  if (rc) return rc;
+  if (stalled) {
+    // FP64 continuation of the stalled rhs from their current solution: the
+    // first FP64 reliable update recomputes r, and p = r (beta = 0)
+    LQCD_HIP(launch_axpby(1.0, m.xl, P_F32, 1.0, m.X, P_F64, n_vec, HRS, FRS, N, st));
+    LQCD_HIP(launch_fill_zero(m.xl, (size_t)N * HRS * 8, st));
+    LQCD_HIP(launch_fill_zero(m.P, full_bytes, st));
+    LQCD_HIP(launch_cg_escalate(cg, N, st));
+    select(false);
+    LQCD_HIP(reliable_update());
+    LQCD_HIP(launch_cg_p(m.P, m.R, P_F64, n_vec, FRS, N, cg, nullptr, P_F32, st));
+    rc = run_phase(stalled);
+    if (rc) return rc;
   }
 
   // ---- reconstruct the odd sites, unpack, FP64 full-lattice residual -------
@@ -468,6 +500,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     info[r].iters = hs[r].iters;
     info[r].reliable_updates = hs[r].rupd;
     info[r].restarts = hs[r].restarts;
+    info[r].fp64_from = hs[r].fp64_from;
+    info[r].reserved = 0;
     info[r].true_residual = (h_eta2[r] > 0.0) ? sqrt(fres[r] / h_eta2[r]) : 0.0;
     info[r].seconds = secs;
     int stt = LQCD_OK;

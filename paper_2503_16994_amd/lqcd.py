@@ -68,10 +68,11 @@ class Tuning(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("reliable_updates", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("fp64_from", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None

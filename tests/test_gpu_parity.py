@@ -134,9 +134,9 @@ def test_schur_operators_fp64(setup):
     assert rel(got, exp) < 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [(lqcd.F32, 2e-6), (lqcd.BF16, 2e-2)])
-def test_reduced_precision_operator(prec, tol):
-    c = OP_CASES[1]
+@pytest.mark.parametrize("prec,tol", [(lqcd.F32, 2e-6), (lqcd.BF16, 2e-2)], ids=["f32", "bf16"])
+@pytest.mark.parametrize("c", OP_CASES[1:4], ids=case_id)
+def test_reduced_precision_operator(c, prec, tol):
     pm = lqcd.PM_F64 | (lqcd.PM_F32 if prec == lqcd.F32 else lqcd.PM_BF16)
     s = Setup(*c, pmask=pm)
     psi = s.fields(1, seed=5)
@@ -153,7 +153,7 @@ def test_reduced_precision_operator(prec, tol):
     for op, ref in cases:
         got = s.apply(psi, op, prec=prec, ws=ws)[0]
         err = rel(got, ref)
-        print(f"prec {prec} op {op}: rel err {err:.3e}")
+        print(f"{case_id(c)} prec {prec} op {op}: rel err {err:.3e}")
         assert err < tol
 
 
@@ -280,3 +280,24 @@ def test_autotune_picks_a_valid_config():
     eta = torch.from_numpy(inputs.point_sources_12(s.L)).cuda()
     r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=lqcd.F32, ws=ws)
     assert r.status == lqcd.OK
+
+
+def test_mixed_precision_stall_continues_in_fp64():
+    """BF16 inner precision on a Schroedinger-functional system whose
+    conditioning it cannot resolve (without the continuation it stagnates at
+    a true residual ~1e-7): the stalled rhs must continue in FP64 and still
+    reach the tolerance, checked with the oracle operator."""
+    L = (8, 8, 8, 32)
+    s = Setup(L, SF, (1, 1, 1, 1), 0.2, 0.134, 1.8, 1.0, seed=4,
+              pmask=lqcd.PM_F64 | lqcd.PM_BF16)
+    eta = np.stack([inputs.point_source(L, (0, 0, 0, 1), 0, 0), inputs.point_source(L, (0, 0, 0, 1), 3, 2)])
+    res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, tol=1e-10,
+                     inner_prec=lqcd.BF16, maxiter=20000)
+    psi = res.psi.cpu().numpy()
+    for j in range(2):
+        rho = _oracle_rho(s, eta[j], psi[j])
+        print(f"SF bf16 rhs {j}: iters {res.info[j]['iters']} fp64 from {res.info[j]['fp64_from']} "
+              f"rho {rho:.3e}")
+        assert rho <= 1e-10
+        assert res.info[j]["fp64_from"] > 0
+    assert res.status == lqcd.OK
