@@ -117,11 +117,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving as specified: 400 requests, then a run at 0.7x the measured capacity")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--profile-kernel", action="store_true",
-                    help="only a 1 GiB calibration copy and hop-kernel launches (counter runs)")
+                    help="only calibration copy/sum and hop-kernel launches (profiler runs)")
     args = ap.parse_args()
+    if args.serve_full and args.serve_requests == 16:
+        args.serve_requests = 400
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent propagators shard across GPUs with no communication; see DESIGN.md)",
@@ -191,9 +195,12 @@ def main():
     del vin, vout
 
     # ---- mixed precision, 12 rhs in one solve ---------------------------------
-    def mixed_leg(g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag):
+    def mixed_leg(g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag, precs=("f64", "f32", "bf16")):
+        """12 rhs in one solve per inner precision (autotuned kernels)."""
         res = {}
-        for name, ip in (("f32", lqcd.F32), ("bf16", lqcd.BF16)):
+        pmap = {"f64": lqcd.F64, "f32": lqcd.F32, "bf16": lqcd.BF16}
+        for name in precs:
+            ip = pmap[name]
             tune, _ = lqcd.autotune(g, lqcd.dirac(kappa, csw), ip, 12, ws, stream=stream)
 
             def mstep():
@@ -204,10 +211,13 @@ def main():
             rho = max(i["true_residual"] for i in r.info)
             sps = 12 / mdt
             res[name] = {"solves_per_s": round(sps, 2), "ms_per_12": round(mdt * 1e3, 2),
-                         "vs_fp64": round(sps / fp64_sps, 3), "converged": bool(r.status == 0 and rho <= TOL),
+                         "vs_fp64_one_at_a_time": round(sps / fp64_sps, 3),
+                         "converged": bool(r.status == 0 and rho <= TOL),
                          "iters": max(i["iters"] for i in r.info), "max_true_residual": rho,
                          "reliable_updates": max(i["reliable_updates"] for i in r.info), "tuning": tune}
-            log(f"mixed {tag} {name} 12-rhs: {res[name]}")
+            if name != "f64":
+                res[name]["fp64_from"] = [i["fp64_from"] for i in r.info]
+            log(f"12-rhs {tag} {name}: {res[name]}")
         return res
 
     mixed = mixed_c4 = c3 = dw_hbm = serving = None
@@ -215,15 +225,20 @@ def main():
         mixed = mixed_leg(gauge, lat, ws12, eta, KAPPA, CSW, value, args.steps, args.warmup, "16^3x32")
         del ws12
         torch.cuda.empty_cache()
-        mixed_c4 = c4_leg(stream, pm, mixed_leg, max(2, args.steps // 3))
+        mixed_c4 = c4_leg(stream, pm, mixed_leg, 1)
 
-    # ---- 32^3x64: Z2 solve in three precisions and the kernels' HBM rates ----
+    # ---- 32^3x64: Z2 solve, 12-source propagator and the kernels' HBM rates --
+    ctx = None
     if not args.no_hbm:
-        c3, dw_hbm = c3_leg(stream, pm, args.no_mixed)
+        c3, dw_hbm = c3_leg(stream, pm, args.no_mixed, mixed_leg)
+        ctx = ctx_leg(stream)
 
     # ---- serving -------------------------------------------------------------
     if not args.no_serve:
-        serving = serve_leg(args.serve_requests, args.serve_rate, U2)
+        serving = {"offered": serve_leg(args.serve_requests, args.serve_rate, U2)}
+        if args.serve_full:
+            cap = serving["offered"]["requests_per_s"]
+            serving["at_0.7_capacity"] = serve_leg(max(20, args.serve_requests // 8), 0.7 * cap, U2, seed=98)
 
     # ---- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
@@ -241,7 +256,7 @@ def main():
                    "lattice": list(L_C2), "kappa": KAPPA, "csw": CSW, "bc": "periodic/antiperiodic",
                    "link_eps": EPS, "sources": 12, "tol": TOL, "solver": "eo-CG FP64, hipGraph chunks"},
         "iters_per_solve": iters, "max_true_residual": rho_max,
-        "roofline": roofline, "mixed": mixed, "mixed_c4": mixed_c4, "c3": c3, "dw_hbm": dw_hbm,
+        "roofline": roofline, "mixed": mixed, "mixed_c4": mixed_c4, "c3": c3, "dw_hbm": dw_hbm, "ctx": ctx,
         "serving": serving, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -275,14 +290,16 @@ def c4_leg(stream, pm, mixed_leg, steps):
     del ws1
     torch.cuda.empty_cache()
     ws12 = lqcd.Workspace(lat4, pm, 12)
-    out.update(mixed_leg(g4, lat4, ws12, eta4, kappa, csw, fp64, steps, 1, "24^3x48 SF"))
+    out["multi_rhs_12"] = mixed_leg(g4, lat4, ws12, eta4, kappa, csw, fp64, steps, 1, "24^3x48 SF")
     del ws12, g4
     torch.cuda.empty_cache()
     return out
 
 
-def c3_leg(stream, pm, no_mixed):
-    """32^3x64: Z2-noise solve in FP64/FP32/BF16 and the hop kernels' HBM rates."""
+def c3_leg(stream, pm, no_mixed, mixed_leg):
+    """32^3x64: Z2-noise solve in FP64/FP32/BF16, the 12-source propagator
+    (FP64 one source at a time vs 12 rhs in one solve) and the hop kernels'
+    HBM rates."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -326,12 +343,63 @@ def c3_leg(stream, pm, no_mixed):
         if name != "f64":
             c3[name]["vs_fp64"] = round(c3["f64"]["seconds"] / dt, 3)
     log(f"C3: {c3}")
-    del ws3, g3, eta3
+    del eta3
+    # 12 point sources at the origin: FP64 one at a time, then 12 rhs per solve
+    etap = torch.from_numpy(inputs.point_sources_12(L3, (0, 0, 0, 0))).cuda()
+    lqcd.autotune(g3, d3, lqcd.F64, 1, ws3, stream=stream)
+
+    def f64_one():
+        return [lqcd.solve(g3, etap[j:j + 1], kappa, CSW, tol=TOL, inner_prec=lqcd.F64, use_graph=True, ws=ws3,
+                           stream=stream).info[0] for j in range(12)]
+    dt, infos = timed(f64_one, 1, 1)
+    fp64 = 12 / dt
+    c3["propagator_12"] = {"fp64_one_at_a_time": {"solves_per_s": round(fp64, 2), "ms_per_12": round(dt * 1e3, 1),
+                                                  "iters": max(i["iters"] for i in infos),
+                                                  "max_true_residual": max(i["true_residual"] for i in infos)}}
+    del ws3
+    torch.cuda.empty_cache()
+    if not no_mixed:
+        ws12 = lqcd.Workspace(lat3, pm, 12)
+        c3["propagator_12"]["multi_rhs_12"] = mixed_leg(g3, lat3, ws12, etap, kappa, CSW, fp64, 1, 1, "32^3x64")
+        del ws12
+    log(f"C3 propagator: {c3['propagator_12']}")
+    del g3, etap
     torch.cuda.empty_cache()
     return c3, dw_hbm
 
 
-def serve_leg(n_requests, rate, U16):
+def ctx_leg(stream):
+    """The shape of the paper's CG timing: 1000 FP64 full-lattice CG
+    iterations on a 32^4 lattice (periodic space, antiperiodic time, one
+    point source).  Context only: the paper's fields, parameters and
+    boundary conditions are not stated."""
+    import torch
+
+    from paper_2503_16994_amd import inputs, lqcd
+    L = (32, 32, 32, 32)
+    U = inputs.gauge_field(L, EPS, seed=5)
+    lat = lqcd.Lattice(L, lqcd.BC_PERIODIC, THETA)
+    g = lqcd.GaugeField(lat, torch.from_numpy(U), lqcd.PM_F64, stream=stream)
+    del U
+    ws = lqcd.Workspace(lat, lqcd.PM_F64, 1)
+    eta = torch.from_numpy(inputs.point_source(L)[None]).cuda()
+
+    def run():
+        return lqcd.solve(g, eta, KAPPA, CSW, tol=1e-30, solver=lqcd.SOLVER_CG_FULL, maxiter=1000,
+                          use_graph=True, ws=ws, stream=stream, raise_on_noconv=False)
+    dt, r = timed(run, 1, 1)
+    out = {"lattice": list(L), "solver": "FP64 full-lattice CG on Dw^+Dw", "iterations": r.info[0]["iters"],
+           "seconds": round(dt, 3), "ms_per_iteration": round(dt / r.info[0]["iters"] * 1e3, 3),
+           "paper_context": {"A100_s": 13.9, "H100_s": 6.46,
+                             "note": "1000 CG iterations at L/a=32 (paper Sec. 3.4 table); fields and "
+                                     "parameters differ"}}
+    log(f"ctx: {out}")
+    del g, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_leg(n_requests, rate, U16, seed=99):
     """Poisson stream of propagator requests through lqcd_submit/lqcd_poll:
     lattices {8^4, 16^3x32, 24^3x48, 32^3x64} x {open, periodic}, kappa uniform
     in [0.125, 0.136], csw 1.9, 1 or 12 point sources, FP32 inner precision,
@@ -353,7 +421,7 @@ def serve_leg(n_requests, rate, U16):
         src = inputs.point_sources_12(L, (0, 0, 0, 0))
         etas[(L, 12)] = (src, np.empty_like(src))
         etas[(L, 1)] = (src[:1].copy(), np.empty_like(src[:1]))
-    rng = np.random.Generator(np.random.PCG64(99))
+    rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1.0 / rate, n_requests)
     reqs = []
     for k in range(n_requests):
@@ -393,15 +461,19 @@ def serve_leg(n_requests, rate, U16):
            "mean_admission_wait_s": round(float(wait_s.mean()), 4),
            "solves_per_s": round(nsolves / wall, 2), "requests_per_s": round(n_requests / wall, 3),
            "wall_s": round(wall, 3), "peak_arena_gib": round(peak / 2**30, 2),
-           "note": "offered load is far above capacity, so latencies measure the backlog"}
+           "statuses": sorted(set(int(done[t][0]) for t in tickets)),
+           "fp64_continuations": int(sum(1 for t in tickets for i in done[t][1] if i["fp64_from"] > 0))}
     log(f"serving: {out}")
     return out
 
 
 def profile_kernels(stream):
-    """Launch sequence for rocprofv3 counter runs: a plain 1 GiB device copy
-    (to calibrate FETCH_SIZE/WRITE_SIZE against known bytes), then 20 launches
-    of each hop kernel in FP64 at 16^3x32 and at 32^3x64 (default tuning)."""
+    """Launch sequence for rocprofv3 runs: a plain 1 GiB device copy (to
+    calibrate FETCH_SIZE/WRITE_SIZE against known bytes, and the copy rate), a
+    1 GiB read-only sum (read rate), then 20 launches of each hop kernel:
+    FP64 at 16^3x32 and at 32^3x64, FP32 and BF16 at 32^3x64 (one rhs,
+    default tuning), and FP32 with 12 rhs at 32^3x64 (rhs tile 3, block
+    order 2)."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -411,24 +483,38 @@ def profile_kernels(stream):
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
+    for _ in range(3):
+        a.sum()
     torch.cuda.synchronize()
     del a, b
+    pm = lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16
     for L in (L_C2, (32, 32, 32, 64)):
+        big = L[3] == 64
         U = inputs.gauge_field(L, EPS, seed=SEED)
         lat = lqcd.Lattice(L, lqcd.BC_PERIODIC, THETA)
-        g = lqcd.GaugeField(lat, torch.from_numpy(U), lqcd.PM_F64, stream=stream)
+        g = lqcd.GaugeField(lat, torch.from_numpy(U), pm if big else lqcd.PM_F64, stream=stream)
         del U
-        ws = lqcd.Workspace(lat, lqcd.PM_F64, 1)
+        nr = 12 if big else 1
+        ws = lqcd.Workspace(lat, pm if big else lqcd.PM_F64, nr)
         d = lqcd.dirac(KAPPA, CSW)
-        vb = lqcd.vec_bytes(lat, lqcd.F64, 1, 2)
-        x = torch.randn(vb // 8, device="cuda", dtype=torch.float64).view(torch.uint8)
-        y = torch.empty(vb, dtype=torch.uint8, device="cuda")
-        for op in (lqcd.OP_HOP_OE, lqcd.OP_HOP_EO):
-            for _ in range(20):
-                lqcd.dw_apply_internal(g, d, x, y, op, lqcd.F64, 1, ws, stream=stream)
-        torch.cuda.synchronize()
-        log(f"profiled {L}")
-        del g, ws, x, y
+        cases = [(lqcd.F64, 1, (1, 1, 1))]
+        if big:
+            cases += [(lqcd.F32, 1, (1, 1, 1)), (lqcd.BF16, 1, (1, 1, 1)), (lqcd.F32, 12, (3, 2, 1))]
+        for prec, nrhs, tune in cases:
+            lqcd.set_tuning(ws, prec, *tune)
+            vb = lqcd.vec_bytes(lat, prec, nrhs, 2)
+            if prec == lqcd.BF16:
+                x = torch.randn(vb // 2, device="cuda").to(torch.bfloat16).view(torch.uint8)
+            else:
+                x = torch.randn(vb // 4, device="cuda").view(torch.uint8)
+            y = torch.empty(vb, dtype=torch.uint8, device="cuda")
+            for op in (lqcd.OP_HOP_OE, lqcd.OP_HOP_EO):
+                for _ in range(20):
+                    lqcd.dw_apply_internal(g, d, x, y, op, prec, nrhs, ws, stream=stream)
+            torch.cuda.synchronize()
+            log(f"profiled {L} prec {prec} nrhs {nrhs} tuning {tune}")
+            del x, y
+        del g, ws
         torch.cuda.empty_cache()
 
 
