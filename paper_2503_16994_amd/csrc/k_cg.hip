@@ -192,9 +192,10 @@ __global__ void k_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, co
 }
 
 // step 2: s = g5 (b - y) with |s|^2 partials (y = Dhat x or Dw x); b, y, s
-// are [rhs][12 * nsp][V2] with spins 2,3 of every parity block negated
+// are tiled 12-component fields (one or two parities per rhs), spins 2,3 (the
+// upper half of every tile) negated
 __global__ void k_ru_sub(const double2* __restrict__ b, const double2* __restrict__ y, double2* s, long n,
-                         long rs, long V2, const CGState* cs, double* partials) {
+                         long rs, const CGState* cs, double* partials) {
   __shared__ double sh[4];
   const int q = blockIdx.y;
   if (ru_skip(cs[q])) return;
@@ -204,7 +205,7 @@ __global__ void k_ru_sub(const double2* __restrict__ b, const double2* __restric
     double2 u = b[o + i], v = y[o + i];
     double2 d = make_double2(u.x - v.x, u.y - v.y);
     acc += d.x * d.x + d.y * d.y;
-    const long k = (i / V2) % 12;  // component index within a parity block
+    const long k = (i % (12 * kTile)) / kTile;  // component index within its tile
     if (k >= 6) d = make_double2(-d.x, -d.y);
     s[o + i] = d;
   }
@@ -350,10 +351,10 @@ hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, in
   k_ru_fold<<<grid, kB, 0, st>>>(X, rsX, xl, rsl, n, s);
   return hipGetLastError();
 }
-hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs, long V2,
+hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs,
                          int nrhs, const CGState* s, double* partials, hipStream_t st) {
   dim3 grid(blas_nblocks(n), nrhs);
-  k_ru_sub<<<grid, kB, 0, st>>>(b, y, s_out, n, rs, V2, s, partials);
+  k_ru_sub<<<grid, kB, 0, st>>>(b, y, s_out, n, rs, s, partials);
   return hipGetLastError();
 }
 hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,

@@ -78,11 +78,12 @@ __device__ inline M3 load_link(const KGeom& g, const double2* U, int x, int y, i
   t = (t + g.L[3]) % g.L[3];
   const long lex = x + (long)g.L[0] * (y + (long)g.L[1] * (z + (long)g.L[2] * t));
   const int p = (x + y + z + t) & 1;
-  const size_t s = (size_t)(lex >> 1), V2 = (size_t)g.V2;
+  const size_t s = (size_t)(lex >> 1);
+  const double2* u = U + (size_t)p * 36 * g.V2p + tix(s, 36) + mu * 9 * kTile;
   M3 r;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    double2 v = U[(size_t)((p * 4 + mu) * 9 + e) * V2 + s];
+    double2 v = u[e * kTile];
     r.m[e] = {v.x, v.y};
   }
   return r;
@@ -151,15 +152,17 @@ __device__ inline void make_block(const M3& E1, const M3& E2, const M3& E3, doub
   for (int i = 0; i < 6; ++i) B[i][i].re += d;
 }
 
+// block B into components c0 .. c0+17 of site s of a tiled 36-component field
 template <typename S>
-__device__ inline void store_packed(S* base, size_t V2, size_t s, const cd (&B)[6][6]) {
-  st(base + 0 * V2 + s, cd{B[0][0].re, B[1][1].re});
-  st(base + 1 * V2 + s, cd{B[2][2].re, B[3][3].re});
-  st(base + 2 * V2 + s, cd{B[4][4].re, B[5][5].re});
+__device__ inline void store_packed(S* field, size_t s, int c0, const cd (&B)[6][6]) {
+  S* base = field + tix(s, 36) + c0 * kTile;
+  st(base + 0 * kTile, cd{B[0][0].re, B[1][1].re});
+  st(base + 1 * kTile, cd{B[2][2].re, B[3][3].re});
+  st(base + 2 * kTile, cd{B[4][4].re, B[5][5].re});
 #pragma unroll
   for (int i = 1; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < i; ++j) st(base + (size_t)tri_index(i, j) * V2 + s, B[i][j]);
+    for (int j = 0; j < i; ++j) st(base + tri_index(i, j) * kTile, B[i][j]);
 }
 
 // Inverse of a Hermitian 6x6 block by LDL^H; returns false on a tiny pivot.
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
   if (s >= g.V2) return;
   const Coord co = site_coord(g, s, p);
   const int x[4] = {co.x, co.y, co.z, co.t};
-  const size_t V2 = (size_t)g.V2;
+  const size_t par = (size_t)p * 36 * g.V2p;  // parity p of the clover field
 
   // planes: 0 xy, 1 xz, 2 xt, 3 yz, 4 yt, 5 zt
   const M3 Fxy = field_strength(g, c.U64, x, 0, 1);
@@ -255,17 +258,15 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
     }
     cd B[6][6];
     make_block(E1, E2, E3, cc, d, B);
-    const size_t off = (size_t)((p * 2 + b) * 18) * V2;
-    store_packed(c.C64 + off, V2, s, B);
-    if (c.C32) store_packed(c.C32 + off, V2, s, B);
-    if (c.C16) store_packed(c.C16 + off, V2, s, B);
+    store_packed(c.C64 + par, s, 18 * b, B);
+    if (c.C32) store_packed(c.C32 + par, s, 18 * b, B);
+    if (c.C16) store_packed(c.C16 + par, s, 18 * b, B);
     if (p == 1) {
       cd R[6][6];
       if (!herm6_inverse(B, R)) atomicOr(c.err_flag, 1);
-      const size_t oi = (size_t)(b * 18) * V2;
-      store_packed(c.Ci64 + oi, V2, s, R);
-      if (c.Ci32) store_packed(c.Ci32 + oi, V2, s, R);
-      if (c.Ci16) store_packed(c.Ci16 + oi, V2, s, R);
+      store_packed(c.Ci64, s, 18 * b, R);
+      if (c.Ci32) store_packed(c.Ci32, s, 18 * b, R);
+      if (c.Ci16) store_packed(c.Ci16, s, 18 * b, R);
     }
   }
 }

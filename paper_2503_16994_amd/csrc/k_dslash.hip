@@ -43,24 +43,24 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
   if (pr == (A)0 && pi == (A)0) return;
 
   const int sn = nb_index(g, s, c, MU, DIR);
-  const size_t V2 = (size_t)g.V2;
+  const size_t par = (size_t)36 * g.V2p;  // one parity of the link field
   const SG* Ub = static_cast<const SG*>(a.U);
-  const SG* up = (DIR > 0) ? Ub + (size_t)((p * 4 + MU) * 9) * V2 + s
-                           : Ub + (size_t)(((1 - p) * 4 + MU) * 9) * V2 + sn;
+  const SG* up = (DIR > 0) ? Ub + p * par + tix(s, 36) + MU * 9 * kTile
+                           : Ub + (1 - p) * par + tix(sn, 36) + MU * 9 * kTile;
   cpx<A> U[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    auto v = ld_nt(up + e * V2);
+    auto v = ld_nt(up + e * kTile);
     U[e] = {(A)v.re, (A)v.im};
   }
 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const SI* yp = yb + (size_t)(rhs0 + r) * a.y_rs + sn;
+    const SI* yp = yb + (size_t)(rhs0 + r) * a.y_rs + tix(sn, 12);
     cpx<A> psi[4][3];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      auto v = ld(yp + k * V2);
+      auto v = ld(yp + k * kTile);
       psi[k / 3][k % 3] = {(A)v.re, (A)v.im};
     }
     cpx<A> h[2][3], w[2][3];
@@ -79,10 +79,11 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
 }
 
 template <typename A, typename SG>
-__device__ inline void load_block(const SG* C, int blk, size_t V2, int s, cpx<A> (&m)[18]) {
+__device__ inline void load_block(const SG* C, int blk, int s, cpx<A> (&m)[18]) {
+  const SG* c = C + tix(s, 36) + blk * 18 * kTile;
 #pragma unroll
   for (int e = 0; e < 18; ++e) {
-    auto v = ld_nt(C + (size_t)(blk * 18 + e) * V2 + s);
+    auto v = ld_nt(c + e * kTile);
     m[e] = {(A)v.re, (A)v.im};
   }
 }
@@ -191,7 +192,6 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
   const int s = bx * SPB + (int)(threadIdx.x / RL);
   ts.s = s;
   ts.active = s < g.V2;
-  const size_t V2 = (size_t)g.V2;
   const SI* yb = static_cast<const SI*>(a.y);
   const SI* zb = static_cast<const SI*>(a.z);
   const SG* cpre = static_cast<const SG*>(a.Cpre);
@@ -236,14 +236,14 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Cm[18];
-      if (PRE == PRE_CLOV) load_block(cpre, b, V2, s, Cm);
+      if (PRE == PRE_CLOV) load_block(cpre, b, s, Cm);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const SI* zp = zb + (size_t)(rhs0 + r) * a.z_rs + s;
+        const SI* zp = zb + (size_t)(rhs0 + r) * a.z_rs + tix(s, 12);
         cpx<A> in6[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-          auto t = ld(zp + (6 * b + i) * V2);
+          auto t = ld(zp + (6 * b + i) * kTile);
           in6[i] = {(A)t.re, (A)t.im};
         }
         if (PRE == PRE_IDENT) {
@@ -262,7 +262,7 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Ci[18];
-      load_block(static_cast<const SG*>(a.Cpost), b, V2, s, Ci);
+      load_block(static_cast<const SG*>(a.Cpost), b, s, Ci);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         cpx<A> in6[6], o6[6];
@@ -295,16 +295,18 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   ThreadSite ts;
   cpx<A> v[NR][12];
   if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL>(a, ts, v)) return;
-  const size_t V2 = (size_t)a.g.V2;
   SO* ob = static_cast<SO*>(a.out);
   if (a.both) ob += ts.p * a.par_stride;
+  // padding sites of the last tile (inactive, v = 0) are written too, so
+  // every output vector holds zeros there
+  const bool store = ts.s < a.g.V2p;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     double nrm = 0.0;
-    if (ts.active) {
-      SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + ts.s;
+    if (store) {
+      SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + tix(ts.s, 12);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) st(op + k * V2, v[r][k]);
+      for (int k = 0; k < 12; ++k) st(op + k * kTile, v[r][k]);
       if (a.partials) {
 #pragma unroll
         for (int k = 0; k < 12; ++k)
@@ -331,7 +333,6 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   ThreadSite ts;
   cpx<A> v[NR][12];
   if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL>(a, ts, v)) return;
-  const size_t V2 = (size_t)a.g.V2;
   SV* xb = static_cast<SV*>(a.xr_x);
   SV* rb = static_cast<SV*>(a.xr_r);
   const SV* pb = static_cast<const SV*>(a.xr_p);
@@ -343,18 +344,18 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
     if (ts.active && !cs.done) {
       const double alpha_d = cs.alpha;
       const AV alpha = (AV)alpha_d;
-      const size_t o = (size_t)q * a.xr_rs + ts.s, ox = (size_t)q * a.xr_xrs + ts.s;
+      const size_t o = (size_t)q * a.xr_rs + tix(ts.s, 12), ox = (size_t)q * a.xr_xrs + tix(ts.s, 12);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        auto pv = ld(pb + o + k * V2);
-        auto xv = ld(xb + ox + k * V2);
-        auto rv = ld(rb + o + k * V2);
+        auto pv = ld(pb + o + k * kTile);
+        auto xv = ld(xb + ox + k * kTile);
+        auto rv = ld(rb + o + k * kTile);
         xv.re += (AV)alpha_d * pv.re;
         xv.im += (AV)alpha_d * pv.im;
         rv.re -= alpha * (AV)v[r][k].re;
         rv.im -= alpha * (AV)v[r][k].im;
-        st(xb + ox + k * V2, xv);
-        st(rb + o + k * V2, rv);
+        st(xb + ox + k * kTile, xv);
+        st(rb + o + k * kTile, rv);
         nrm += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
       }
     }

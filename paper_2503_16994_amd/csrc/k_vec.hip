@@ -43,11 +43,11 @@ __global__ void k_import_gauge(KGeom g, const double2* __restrict__ Uc, double2*
   const int p = (x + y + z + t) & 1;
   const long s = lex >> 1;
   const bool zero = (g.bc == BC_OPEN) && (mu == 3) && (t == g.L[3] - 1);
-  const size_t V2 = (size_t)g.V2;
+  const size_t base = (size_t)p * 36 * g.V2p + tix(s, 36) + mu * 9 * kTile;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
     double2 v = zero ? make_double2(0.0, 0.0) : Uc[i * 9 + e];
-    const size_t o = (size_t)((p * 4 + mu) * 9 + e) * V2 + s;
+    const size_t o = base + e * kTile;
     U64[o] = v;
     if (U32) st(U32 + o, cpx<double>{v.x, v.y});
     if (U16) st(U16 + o, cpx<double>{v.x, v.y});
@@ -62,14 +62,24 @@ hipError_t launch_import_gauge(const KGeom& g, const double2* Uc, double2* U64, 
 }
 
 // ---------------------------------------------------------------------------
-// Spinor pack / unpack: canonical [rhs][lex][12] <-> internal [rhs][p][k][s]
+// Spinor pack / unpack: canonical [rhs][lex][12] <-> internal [rhs][p] tiled
+// 12-component fields.  Pack also zeroes the padding sites of both parities.
 // ---------------------------------------------------------------------------
 template <typename S>
 __global__ void k_pack(KGeom g, const double2* __restrict__ canon, S* out, bool g5) {
   const long V = 2L * g.V2;
   const long lex = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (lex >= V) return;
+  const size_t vec = (size_t)r * 24 * g.V2p;
+  if (lex >= V) {
+    const long pad = g.V2p - g.V2, j = lex - V;
+    if (j >= 2 * pad) return;
+    const long ps = j / pad, sp = g.V2 + j % pad;
+    S* dst = out + vec + (size_t)ps * 12 * g.V2p + tix(sp, 12);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) st(dst + k * kTile, cpx<double>{0.0, 0.0});
+    return;
+  }
   const int x = (int)(lex % g.L[0]);
   long q = lex / g.L[0];
   const int y = (int)(q % g.L[1]);
@@ -78,14 +88,13 @@ __global__ void k_pack(KGeom g, const double2* __restrict__ canon, S* out, bool 
   const int t = (int)(q / g.L[2]);
   const int p = (x + y + z + t) & 1;
   const long s = lex >> 1;
-  const size_t V2 = (size_t)g.V2;
   const double2* src = canon + ((size_t)r * V + lex) * 12;
-  S* dst = out + (size_t)r * 24 * V2 + (size_t)p * 12 * V2 + s;
+  S* dst = out + vec + (size_t)p * 12 * g.V2p + tix(s, 12);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     double2 v = src[k];
     if (g5 && k >= 6) v = make_double2(-v.x, -v.y);
-    st(dst + k * V2, cpx<double>{v.x, v.y});
+    st(dst + k * kTile, cpx<double>{v.x, v.y});
   }
 }
 
@@ -103,20 +112,19 @@ __global__ void k_unpack(KGeom g, const S* __restrict__ in, double2* canon) {
   const int t = (int)(q / g.L[2]);
   const int p = (x + y + z + t) & 1;
   const long s = lex >> 1;
-  const size_t V2 = (size_t)g.V2;
-  const S* src = in + (size_t)r * 24 * V2 + (size_t)p * 12 * V2 + s;
+  const S* src = in + (size_t)r * 24 * g.V2p + (size_t)p * 12 * g.V2p + tix(s, 12);
   double2* dst = canon + ((size_t)r * V + lex) * 12;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    auto v = ld(src + k * V2);
+    auto v = ld(src + k * kTile);
     dst[k] = make_double2((double)v.re, (double)v.im);
   }
 }
 
 hipError_t launch_pack(const KGeom& g, const double2* canon, void* internal, int prec, int nrhs,
                        bool g5, hipStream_t st) {
-  const long V = 2L * g.V2;
-  dim3 grid((unsigned)((V + 255) / 256), nrhs);
+  const long n = 2L * g.V2p;  // every site of both parities, padding included
+  dim3 grid((unsigned)((n + 255) / 256), nrhs);
   if (prec == P_F64) k_pack<double2><<<grid, 256, 0, st>>>(g, canon, (double2*)internal, g5);
   else if (prec == P_F32) k_pack<float2><<<grid, 256, 0, st>>>(g, canon, (float2*)internal, g5);
   else k_pack<bf16x2><<<grid, 256, 0, st>>>(g, canon, (bf16x2*)internal, g5);
@@ -293,13 +301,15 @@ hipError_t launch_fill_zero(void* x, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-// g5 on a half vector [rhs][k][s]: negate k >= 6
+// g5 on a half vector (one parity, tiled 12-component field): negate
+// components k >= 6, i.e. the upper half of every tile
 template <typename S>
-__global__ void k_g5(S* x, long V2, long rs) {
+__global__ void k_g5(S* x, long V2p, long rs) {
   const int q = blockIdx.y;
-  const long n = 6 * V2;
+  const long n = 6 * V2p;
+  constexpr long half = 6 * kTile;
   for (long i = (long)blockIdx.x * kVecBlock + threadIdx.x; i < n; i += (long)gridDim.x * kVecBlock) {
-    S* p = x + (size_t)q * rs + 6 * V2 + i;
+    S* p = x + (size_t)q * rs + (i / half) * 2 * half + half + i % half;
     auto v = ld(p);
     v.re = -v.re;
     v.im = -v.im;
@@ -307,11 +317,11 @@ __global__ void k_g5(S* x, long V2, long rs) {
   }
 }
 
-hipError_t launch_g5(void* x, int prec, long V2, long rs, int nrhs, hipStream_t st) {
-  dim3 grid(blas_nblocks(6 * V2), nrhs);
-  if (prec == P_F64) k_g5<double2><<<grid, kVecBlock, 0, st>>>((double2*)x, V2, rs);
-  else if (prec == P_F32) k_g5<float2><<<grid, kVecBlock, 0, st>>>((float2*)x, V2, rs);
-  else k_g5<bf16x2><<<grid, kVecBlock, 0, st>>>((bf16x2*)x, V2, rs);
+hipError_t launch_g5(void* x, int prec, long V2p, long rs, int nrhs, hipStream_t st) {
+  dim3 grid(blas_nblocks(6 * V2p), nrhs);
+  if (prec == P_F64) k_g5<double2><<<grid, kVecBlock, 0, st>>>((double2*)x, V2p, rs);
+  else if (prec == P_F32) k_g5<float2><<<grid, kVecBlock, 0, st>>>((float2*)x, V2p, rs);
+  else k_g5<bf16x2><<<grid, kVecBlock, 0, st>>>((bf16x2*)x, V2p, rs);
   return hipGetLastError();
 }
 

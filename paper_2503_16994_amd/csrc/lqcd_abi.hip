@@ -78,11 +78,13 @@ extern "C" int lqcd_geom(const lqcd_geom_desc* d, lqcd_geom_t** out) {
   g->desc = *d;
   g->V = V;
   g->V2 = (int)(V / 2);
+  g->V2p = (int)padded_sites(g->V2);
   KGeom& k = g->kg;
   memset(&k, 0, sizeof(k));
   for (int mu = 0; mu < 4; ++mu) k.L[mu] = d->L[mu];
   k.Lxh = d->L[0] / 2;
   k.V2 = g->V2;
+  k.V2p = g->V2p;
   k.sy = k.Lxh;
   k.sz = k.Lxh * d->L[1];
   k.st = k.Lxh * d->L[1] * d->L[2];
@@ -110,7 +112,7 @@ extern "C" int64_t lqcd_geom_volume(const lqcd_geom_t* g) { return g ? g->V : 0;
 // ---------------------------------------------------------------------------
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-static size_t link_elems(const lqcd_geom_t* g) { return (size_t)2 * 4 * 9 * g->V2; }
+static size_t link_elems(const lqcd_geom_t* g) { return (size_t)2 * 36 * g->V2p; }
 
 extern "C" size_t lqcd_gauge_bytes(const lqcd_geom_t* g, int pmask) {
   if (!g) return 0;
@@ -175,7 +177,7 @@ WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base) {
     off += align_up(bytes);
     return r;
   };
-  const size_t V2 = (size_t)g->V2;
+  const size_t V2 = (size_t)g->V2p;  // field rows: sites per parity incl. padding
   m.C64 = (double2*)take(72 * V2 * 16);
   m.Ci64 = (double2*)take(36 * V2 * 16);
   if (pmask & LQCD_PM_F32) {
@@ -211,7 +213,7 @@ WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base) {
     m.qb = (bf16x2*)take(half16);
     m.tb = (bf16x2*)take(half16);
   }
-  const int hop_parts = 2 * (int)((V2 + 63) / 64);  // up to 4 rhs lanes per site
+  const int hop_parts = 2 * (int)((g->V2 + 63) / 64);  // up to 4 rhs lanes per site
   m.max_parts = hop_parts > 2048 ? hop_parts : 2048;
   m.partials = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
   m.partials2 = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
@@ -259,7 +261,7 @@ extern "C" void lqcd_ws_free(lqcd_ws_t* w) {
 
 extern "C" size_t lqcd_vec_bytes(const lqcd_geom_t* g, int prec, int nrhs, int nparity) {
   if (!g || nrhs < 1 || nparity < 1 || nparity > 2 || prec < 0 || prec > 2) return 0;
-  return (size_t)nrhs * nparity * 12 * g->V2 * elem_bytes(prec);
+  return (size_t)nrhs * nparity * 12 * g->V2p * elem_bytes(prec);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,8 +358,8 @@ static HopLaunch base_launch(const OpCtx& c) {
 }
 
 // full-layout element strides
-static long full_rs(const lqcd_geom_t* g) { return 24L * g->V2; }
-static long par_off(const lqcd_geom_t* g) { return 12L * g->V2; }
+static long full_rs(const lqcd_geom_t* g) { return 24L * g->V2p; }
+static long par_off(const lqcd_geom_t* g) { return 12L * g->V2p; }
 
 static char* elem_ptr(void* base, int prec, long elems) {
   return (char*)base + (size_t)elems * elem_bytes(prec);
@@ -369,7 +371,7 @@ static hipError_t apply_dw_full(const OpCtx& c, const void* y, void* out, bool g
   HopLaunch h = base_launch(c);
   h.both = true;
   h.par_stride = par_off(g);
-  h.cpre_par = 36L * g->V2;
+  h.cpre_par = 36L * g->V2p;
   h.y = y;
   h.z = y;
   h.out = out;
@@ -448,7 +450,7 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
     vout = w->m.TMP;
     LQCD_HIP(launch_pack(g->kg, (const double2*)in, (void*)vin, prec, nrhs, g5in, st));
   }
-  const size_t full_bytes = (size_t)nrhs * 24 * g->V2 * elem_bytes(prec);
+  const size_t full_bytes = (size_t)nrhs * 24 * g->V2p * elem_bytes(prec);
   void* tmp = w->m.R;  // scratch full vector
   void* tmp2 = w->m.P;
   switch (op) {
@@ -459,7 +461,7 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
     case LQCD_OP_DW_DAG:
       if (!canon) {  // g5 on the input of an internal vector: copy with g5
         LQCD_HIP(hipMemcpyAsync(tmp2, vin, full_bytes, hipMemcpyDeviceToDevice, st));
-        LQCD_HIP(launch_g5(tmp2, prec, g->V2, 12L * g->V2, 2 * nrhs, st));
+        LQCD_HIP(launch_g5(tmp2, prec, g->V2p, 12L * g->V2p, 2 * nrhs, st));
         vin = tmp2;
       }
       LQCD_HIP(apply_dw_full(c, vin, vout, true, nullptr));
@@ -472,7 +474,7 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
     case LQCD_OP_SCHUR_DAG:
       if (op == LQCD_OP_SCHUR_DAG && !canon) {
         LQCD_HIP(hipMemcpyAsync(tmp2, vin, full_bytes, hipMemcpyDeviceToDevice, st));
-        LQCD_HIP(launch_g5(tmp2, prec, g->V2, 12L * g->V2, 2 * nrhs, st));
+        LQCD_HIP(launch_g5(tmp2, prec, g->V2p, 12L * g->V2p, 2 * nrhs, st));
         vin = tmp2;
       }
       if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
@@ -533,7 +535,7 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   int rc = ensure_clover(u, d, w, st);
   if (rc) return rc;
   // operands: two full-layout vectors of the FP64 slots (wide enough for any precision)
-  const size_t full_bytes = (size_t)nrhs * 24 * w->g->V2 * elem_bytes(prec);
+  const size_t full_bytes = (size_t)nrhs * 24 * w->g->V2p * elem_bytes(prec);
   LQCD_HIP(launch_fill_zero(w->m.X, full_bytes, st));
   hipEvent_t e0, e1;
   LQCD_HIP(hipEventCreate(&e0));

@@ -2,18 +2,25 @@
 // types, even-odd site geometry, spin projection of the hopping term and the
 // 6x6 clover block algebra.
 //
-// Internal layout (all "site-coalesced": consecutive lanes of a wavefront
-// touch consecutive sites of one parity, so every load below is a unit-stride
-// 64-lane access):
+// Internal layout, tiled structure-of-arrays: the sites of one parity are
+// grouped in tiles of kTile = 64 (one wavefront), and a field with nc complex
+// components per site stores tile after tile, each tile as nc rows of 64
+// sites.  Component k of site s is at  tix(s, nc) + 64 k,  so the 64 lanes of
+// a wavefront that own the 64 sites of a tile make unit-stride loads, and the
+// components of a site are 512 B (FP32) to 1 KiB (FP64) apart instead of a
+// whole parity plane (a power of two of MiB on the benchmark lattices, which
+// maps every component of a site onto the same L2 set).
 //   site index     s = lex >> 1 within parity p = (x+y+z+t) & 1, where
-//                  lex = x + Lx (y + Ly (z + Lz t)) and V2 = V/2;
-//   spinor         psi[rhs][k][s], k = 3*spin + colour (12 complex / site);
-//   links          U[p][mu][3*a+b][s] (9 complex per site and direction);
-//   clover block   C[p][blk][e][s], blk = chirality (spins 0,1 / 2,3),
-//                  e = 0..2 the six real diagonal entries as pairs,
-//                  e = 3..17 the 15 complex strictly-lower entries (i>j) in
-//                  row order; the block is Hermitian;
-//   odd inverse    Ci[blk][e][s] with the same packing.
+//                  lex = x + Lx (y + Ly (z + Lz t)), V2 = V/2 sites and
+//                  V2p = V2 rounded up to a multiple of kTile (padding sites
+//                  hold zeros in vectors and are never read by the stencil);
+//   spinor         psi[rhs][p] = 12-component field, k = 3*spin + colour;
+//   links          U[p] = 36-component field, component 9*mu + 3*a + b;
+//   clover block   C[p] = 36-component field, component 18*blk + e,
+//                  blk = chirality (spins 0,1 / 2,3), e = 0..2 the six real
+//                  diagonal entries as pairs, e = 3..17 the 15 complex
+//                  strictly-lower entries (i>j) in row order (Hermitian);
+//   odd inverse    Ci = 36-component field (odd sites) with the same packing.
 // Every stored element is one complex number: double2 (FP64), float2 (FP32)
 // or two bfloat16 packed in a uint32 (BF16, re in the low half).
 #pragma once
@@ -22,6 +29,14 @@
 #include <stdint.h>
 
 namespace lqcd {
+
+constexpr int kTile = 64;
+
+// offset of component 0 of site s in a tiled field with nc components per site
+__host__ __device__ inline size_t tix(size_t s, int nc) {
+  return (s >> 6) * (size_t)(nc * kTile) + (s & (kTile - 1));
+}
+__host__ __device__ inline long padded_sites(long v2) { return (v2 + kTile - 1) / kTile * kTile; }
 
 // ---------------------------------------------------------------------------
 // Storage element types and conversion to the accumulation type
@@ -195,6 +210,7 @@ struct KGeom {
   int L[4];       // Lx, Ly, Lz, T
   int Lxh;        // Lx / 2
   int V2;         // sites per parity
+  int V2p;        // V2 rounded up to a multiple of kTile (tiled field rows)
   int sy, sz, st; // eo-index strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
   int bc;
   FastDiv div_xh, div_y, div_z;

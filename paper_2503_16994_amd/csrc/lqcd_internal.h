@@ -15,6 +15,7 @@ struct lqcd_geom {
   lqcd::KGeom kg;
   int64_t V;
   int V2;
+  int V2p;  // V2 rounded up to the 64-site layout tile
 };
 
 struct lqcd_gauge {
@@ -29,15 +30,15 @@ struct lqcd_gauge {
 // Device memory map of a workspace (all pointers into the caller's memory).
 struct WsLayout {
   size_t bytes = 0;
-  // clover: A on both parities [2][2][18][V2], inverse on odd sites [2][18][V2]
+  // clover: A on both parities (tiled 36-component fields), inverse on the odd sites
   double2 *C64 = nullptr, *Ci64 = nullptr;
   float2 *C32 = nullptr, *Ci32 = nullptr;
   lqcd::bf16x2 *C16 = nullptr, *Ci16 = nullptr;
   int* err_flag = nullptr;
-  // FP64 full-lattice vectors [nrhs][2][12][V2]
+  // FP64 full-lattice vectors [nrhs][2 parities] of tiled 12-component fields
   double2 *E = nullptr, *X = nullptr, *TMP = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr,
           *AP = nullptr, *EH = nullptr;
-  // inner-precision half vectors [nrhs][12][V2] (FP32 storage) and BF16 copies
+  // inner-precision half vectors [nrhs] of tiled 12-component fields (FP32) and BF16 copies
   float2 *xl = nullptr, *rl = nullptr, *pl = nullptr, *ql = nullptr, *apl = nullptr, *tl = nullptr;
   lqcd::bf16x2 *pb = nullptr, *qb = nullptr, *tb = nullptr;
   // reductions

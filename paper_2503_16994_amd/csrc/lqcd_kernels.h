@@ -32,7 +32,7 @@ struct HopLaunch {
   const void* U;     // links (both parities), precision prec
   const void* y;     // opposite-parity input
   const void* z;     // same-parity input (PRE_IDENT / PRE_CLOV)
-  const void* Cpre;  // clover blocks of parity p_out (2 x 18 x V2)
+  const void* Cpre;  // clover blocks of parity p_out (tiled 36-component field)
   const void* Cpost; // clover inverse blocks of parity p_out
   void* out;
   long y_rs, z_rs, out_rs;
@@ -92,8 +92,8 @@ struct CloverLaunch {
   KGeom g;
   const double2* U64;
   double m0, csw, cF;
-  double2* C64;     // [2][2][18][V2]
-  double2* Ci64;    // [2][18][V2] odd inverse
+  double2* C64;     // two parities, each a tiled 36-component field
+  double2* Ci64;    // tiled 36-component field: inverse on the odd sites
   float2* C32;
   float2* Ci32;
   bf16x2* C16;
@@ -169,7 +169,7 @@ hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nr
 hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);
 hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs,
-                         long V2, int nrhs, const CGState* s, double* partials, hipStream_t st);
+                         int nrhs, const CGState* s, double* partials, hipStream_t st);
 hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);
 hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r,
@@ -190,6 +190,6 @@ hipError_t launch_sub_norm(const double2* x, const double2* y, double2* out, lon
                            int nrhs, double* partials, hipStream_t st);
 hipError_t launch_fill_zero(void* x, size_t bytes, hipStream_t st);
 // x (even half vector) *= g5 in place
-hipError_t launch_g5(void* x, int prec, long V2, long rs, int nrhs, hipStream_t st);
+hipError_t launch_g5(void* x, int prec, long V2p, long rs, int nrhs, hipStream_t st);
 
 }  // namespace lqcd

@@ -164,7 +164,7 @@ int iter_parts(const Ctl& c, int lprec) { return hop_nparts(mk(c, lprec)); }
 hipError_t dw_full(const Ctl& c, const double2* y, double2* out, bool g5, double* partials,
                    const int* done) {
   HopLaunch h = mk(c, P_F64);
-  const long V2 = c.g->V2;
+  const long V2 = c.g->V2p;  // field rows per parity
   h.in_prec = h.out_prec = P_F64;
   h.both = true;
   h.par_stride = 12 * V2;
@@ -246,7 +246,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   if (rc) return rc;
 
   const lqcd_geom_t* g = w->g;
-  const long V2 = g->V2;
+  const long V2 = g->V2p;  // field rows per parity (sites incl. padding)
   const WsLayout& m = w->m;
   Ctl c{st, g, u, w, N};
   const long FRS = 24 * V2, HRS = 12 * V2;
@@ -288,7 +288,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   CGState* cg = m.cg;
   const int* done = &cg[0].done;
   const int* skip_ru = &cg[0].skip_ru;
-  const int nb_hop = (int)((V2 + 255) / 256);
+  const int nb_hop = (int)((g->V2 + 255) / 256);  // site blocks of an FP64 hop launch
 
   LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
   LQCD_HIP(launch_fill_zero(m.X, full_bytes, st));
@@ -363,14 +363,14 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       if (lo && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
       if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, 1))) return e;
       if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, 1))) return e;
-      if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, V2, N, cg, parts2, st))) return e;
+      if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, N, cg, parts2, st))) return e;
       if ((e = hop_eo(c, P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
       if ((e = hop_oe(c, P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, 1))) return e;
       if (lo && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
       return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_hop, N, st);
     }
     if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
-    if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, V2, N, cg, parts2, st))) return e;
+    if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, N, cg, parts2, st))) return e;
     if ((e = dw_full(c, m.AP, m.R, true, parts, skip_ru))) return e;
     return launch_ru_finish(cg, parts2, blas_nblocks(24 * V2), parts, 2 * nb_hop, N, st);
   };

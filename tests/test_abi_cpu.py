@@ -80,6 +80,12 @@ def test_geometry_sizes():
     assert lib.lqcd_ws_bytes(h, lqcd.PM_F64, 12) > lib.lqcd_ws_bytes(h, lqcd.PM_F64, 1)
     assert lib.lqcd_ws_bytes(h, lqcd.PM_F64, 0) == 0
     lib.lqcd_geom_free(h)
+    # ragged: V/2 = 288 sites per parity are stored in 5 tiles of 64 (320 rows)
+    assert lib.lqcd_geom(ctypes.byref(_desc(lqcd, (6, 4, 4, 6))), ctypes.byref(h)) == lqcd.OK
+    assert lib.lqcd_vec_bytes(h, lqcd.F64, 1, 2) == 2 * 12 * 320 * 16
+    assert lib.lqcd_vec_bytes(h, lqcd.F32, 3, 1) == 3 * 12 * 320 * 8
+    assert lib.lqcd_gauge_bytes(h, lqcd.PM_F64) >= 2 * 36 * 320 * 16
+    lib.lqcd_geom_free(h)
 
 
 def test_null_and_bad_arguments_are_rejected_without_device_work():
