@@ -185,8 +185,10 @@ typedef struct lqcd_tuning {
                           after the other */
   int32_t rhs_lanes;   /* lanes sharing one site, each with its own nr_tile
                           rhs: 1, 2 or 4 (FP64 uses 1) */
-  int32_t reserved;
+  int32_t flags;       /* LQCD_TUNE_NT_STORE: the hop kernels write their
+                          output spinors with non-temporal stores */
 } lqcd_tuning;
+enum { LQCD_TUNE_NT_STORE = 1 };
 
 /* Hop-kernel configuration used by a workspace for precision `prec`
  * (default: nr_tile 1, block_order 1, rhs_lanes 1).  A launch over n rhs uses
@@ -197,7 +199,7 @@ int lqcd_ws_set_tuning(lqcd_ws_t *w, int prec, const lqcd_tuning *t);
 int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
 
 /* Autotuner: times every candidate configuration (nr_tile x rhs_lanes
- * dividing nrhs, block_order) of one Schur-operator application (both hop kernels)
+ * dividing nrhs, block_order, flags) of one Schur-operator application (both hop kernels)
  * in precision `prec` on nrhs fields of the workspace, with HIP events on
  * `stream`, at the workspace's real lattice shape; stores the fastest in the
  * workspace and returns it with its time in microseconds.  Overwrites the

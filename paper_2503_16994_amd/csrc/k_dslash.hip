@@ -305,8 +305,13 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
     double nrm = 0.0;
     if (store) {
       SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + tix(ts.s, 12);
+      if (a.nt_out) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) st(op + k * kTile, v[r][k]);
+        for (int k = 0; k < 12; ++k) st_nt(op + k * kTile, v[r][k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) st(op + k * kTile, v[r][k]);
+      }
       if (a.partials) {
 #pragma unroll
         for (int k = 0; k < 12; ++k)

@@ -139,6 +139,24 @@ __device__ inline cpx<float> ld_nt(const bf16x2* p) {
   return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
 }
 
+// Non-temporal (streaming) vector stores: for outputs written once per
+// launch, so that they do not displace re-read data from L2.
+template <typename A>
+__device__ inline void st_nt(double2* p, cpx<A> c) {
+  nt_d2 v = {(double)c.re, (double)c.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_d2*>(p));
+}
+template <typename A>
+__device__ inline void st_nt(float2* p, cpx<A> c) {
+  nt_f2 v = {(float)c.re, (float)c.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f2*>(p));
+}
+template <typename A>
+__device__ inline void st_nt(bf16x2* p, cpx<A> c) {
+  const uint32_t v = f32_to_bf16_rne((float)c.re) | (f32_to_bf16_rne((float)c.im) << 16);
+  __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(p));
+}
+
 // Block index remap for the 8 XCDs of the MI355X.  Workgroups are handed to
 // the XCDs round-robin (workgroup b runs on XCD b mod 8, each XCD with its own
 // L2); this maps the b-th workgroup to logical block

@@ -69,7 +69,7 @@ struct lqcd_ws {
   double kappa = 0, csw = 0, cF = 0;
   int clover_pmask = 0;
   std::vector<GraphEntry> graphs;
-  lqcd_tuning tune[3] = {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}};  // nr, order, lanes
+  lqcd_tuning tune[3] = {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}};  // nr, order, lanes, flags
 };
 
 namespace lqcd {
@@ -112,6 +112,7 @@ inline void apply_tuning(HopLaunch& h, const lqcd_tuning& t) {
   h.nr_tile = nr;
   h.rhs_lanes = rl;
   h.order = t.block_order;
+  h.nt_out = (t.flags & LQCD_TUNE_NT_STORE) ? 1 : 0;
 }
 inline void single_tile(HopLaunch& h) {
   h.nr_tile = 1;

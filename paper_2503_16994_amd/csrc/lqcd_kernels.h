@@ -55,6 +55,7 @@ struct HopLaunch {
   // number of lanes that share a site and split its rhs (1, 2, 4)
   int order;
   int rhs_lanes;
+  int nt_out;  // 1: non-temporal stores of the output spinor
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
   int bpp;  // site blocks per (z, t) plane

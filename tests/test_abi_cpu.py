@@ -100,3 +100,28 @@ def test_null_and_bad_arguments_are_rejected_without_device_work():
     t = lqcd.Tuning(1, 1, 0, 0)
     assert lib.lqcd_ws_set_tuning(None, 0, ctypes.byref(t)) == lqcd.EINVAL
     assert lib.lqcd_autotune(None, None, 0, 1, None, None, None, None) == lqcd.EINVAL
+
+
+def test_tuning_values_are_validated():
+    """lqcd_ws_create only records the caller's pointer, so a workspace over a
+    host buffer (never dereferenced here) suffices to check the tuning API."""
+    import numpy as np
+    lqcd, lib = _lib()
+    g = ctypes.c_void_p()
+    assert lib.lqcd_geom(ctypes.byref(_desc(lqcd, (4, 4, 4, 4))), ctypes.byref(g)) == lqcd.OK
+    nbytes = lib.lqcd_ws_bytes(g, lqcd.PM_F64 | lqcd.PM_F32, 2)
+    buf = np.zeros(nbytes + 256, np.uint8)
+    addr = (buf.ctypes.data + 255) // 256 * 256
+    w = ctypes.c_void_p()
+    assert lib.lqcd_ws_create(g, lqcd.PM_F64 | lqcd.PM_F32, 2, ctypes.c_void_p(addr), nbytes, ctypes.byref(w)) == lqcd.OK
+    ok = lqcd.Tuning(2, 4, 2, lqcd.TUNE_NT_STORE)
+    assert lib.lqcd_ws_set_tuning(w, lqcd.F32, ctypes.byref(ok)) == lqcd.OK
+    back = lqcd.Tuning()
+    assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK
+    assert back.as_dict() == {"nr_tile": 2, "block_order": 4, "rhs_lanes": 2, "nt_store": True}
+    for bad in (lqcd.Tuning(5, 1, 1, 0), lqcd.Tuning(1, 5, 1, 0), lqcd.Tuning(1, 1, 3, 0), lqcd.Tuning(1, 1, 1, 2)):
+        assert lib.lqcd_ws_set_tuning(w, lqcd.F32, ctypes.byref(bad)) == lqcd.EINVAL
+    assert lib.lqcd_ws_set_tuning(w, 3, ctypes.byref(ok)) == lqcd.EINVAL
+    assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK and back.flags == lqcd.TUNE_NT_STORE
+    lib.lqcd_ws_free(w)
+    lib.lqcd_geom_free(g)
