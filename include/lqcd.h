@@ -186,9 +186,12 @@ typedef struct lqcd_tuning {
   int32_t rhs_lanes;   /* lanes sharing one site, each with its own nr_tile
                           rhs: 1, 2 or 4 (FP64 uses 1) */
   int32_t flags;       /* LQCD_TUNE_NT_STORE: the hop kernels write their
-                          output spinors with non-temporal stores */
+                          output spinors with non-temporal stores;
+                          LQCD_TUNE_CACHED_GAUGE: links and clover blocks
+                          are read with ordinary (cached) loads instead of
+                          non-temporal ones */
 } lqcd_tuning;
-enum { LQCD_TUNE_NT_STORE = 1 };
+enum { LQCD_TUNE_NT_STORE = 1, LQCD_TUNE_CACHED_GAUGE = 2 };
 
 /* Hop-kernel configuration used by a workspace for precision `prec`
  * (default: nr_tile 1, block_order 1, rhs_lanes 1).  A launch over n rhs uses

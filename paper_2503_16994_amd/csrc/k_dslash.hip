@@ -50,7 +50,7 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
   cpx<A> U[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    auto v = ld_nt(up + e * kTile);
+    auto v = a.cached_gauge ? ld(up + e * kTile) : ld_nt(up + e * kTile);
     U[e] = {(A)v.re, (A)v.im};
   }
 
@@ -79,11 +79,11 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
 }
 
 template <typename A, typename SG>
-__device__ inline void load_block(const SG* C, int blk, int s, cpx<A> (&m)[18]) {
+__device__ inline void load_block(const SG* C, int blk, int s, bool cached, cpx<A> (&m)[18]) {
   const SG* c = C + tix(s, 36) + blk * 18 * kTile;
 #pragma unroll
   for (int e = 0; e < 18; ++e) {
-    auto v = ld_nt(c + e * kTile);
+    auto v = cached ? ld(c + e * kTile) : ld_nt(c + e * kTile);
     m[e] = {(A)v.re, (A)v.im};
   }
 }
@@ -236,7 +236,7 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Cm[18];
-      if (PRE == PRE_CLOV) load_block(cpre, b, s, Cm);
+      if (PRE == PRE_CLOV) load_block(cpre, b, s, a.cached_gauge != 0, Cm);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const SI* zp = zb + (size_t)(rhs0 + r) * a.z_rs + tix(s, 12);
@@ -262,7 +262,7 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Ci[18];
-      load_block(static_cast<const SG*>(a.Cpost), b, s, Ci);
+      load_block(static_cast<const SG*>(a.Cpost), b, s, a.cached_gauge != 0, Ci);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         cpx<A> in6[6], o6[6];

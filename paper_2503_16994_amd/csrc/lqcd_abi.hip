@@ -509,7 +509,7 @@ extern "C" int lqcd_ws_set_tuning(lqcd_ws_t* w, int prec, const lqcd_tuning* t) 
   if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: null pointer");
   if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: bad precision %d", prec);
   if (t->nr_tile < 1 || t->nr_tile > 4 || t->block_order < 0 || t->block_order > 4 ||
-      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~LQCD_TUNE_NT_STORE))
+      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE)))
     return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: value out of range");
   w->tune[prec] = *t;
   return LQCD_OK;
@@ -548,8 +548,9 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
     if (nrhs % rl || (prec == P_F64 && rl > 1)) continue;
     for (int nr = 1; nr <= 4 && err == hipSuccess; ++nr) {
       if (nrhs % (nr * rl)) continue;
-      for (int cfg = 0; cfg < 10 && err == hipSuccess; ++cfg) {
-        const int order = cfg >> 1, flags = (cfg & 1) ? LQCD_TUNE_NT_STORE : 0;
+      for (int cfg = 0; cfg < 20 && err == hipSuccess; ++cfg) {
+        const int order = cfg >> 2;
+        const int flags = ((cfg & 1) ? LQCD_TUNE_NT_STORE : 0) | ((cfg & 2) ? LQCD_TUNE_CACHED_GAUGE : 0);
         w->tune[prec] = lqcd_tuning{nr, order, rl, flags};
         auto once = [&]() -> hipError_t {
           hipError_t e = apply_hop_eo(c, w->m.X, w->m.R);

@@ -55,7 +55,9 @@ struct HopLaunch {
   // number of lanes that share a site and split its rhs (1, 2, 4)
   int order;
   int rhs_lanes;
-  int nt_out;  // 1: non-temporal stores of the output spinor
+  int nt_out;        // 1: non-temporal stores of the output spinor
+  int cached_gauge;  // 1: ordinary (cached) loads of links and clover blocks
+                     // instead of non-temporal ones (rhs tiles re-read them)
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
   int bpp;  // site blocks per (z, t) plane

@@ -29,6 +29,7 @@ BC_PERIODIC, BC_SF, BC_OPEN = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 PM_F64, PM_F32, PM_BF16 = 1, 2, 4
 TUNE_NT_STORE = 1  # lqcd_tuning.flags: non-temporal output stores in the hop kernels
+TUNE_CACHED_GAUGE = 2  # lqcd_tuning.flags: cached (not non-temporal) link and clover loads
 # operators
 (OP_DW, OP_DW_DAG, OP_G5DW, OP_DWDAGDW, OP_SCHUR, OP_SCHUR_DAG, OP_SCHUR_NORMAL, OP_HOP_EO,
  OP_HOP_OE) = range(9)
@@ -64,7 +65,7 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {"nr_tile": self.nr_tile, "block_order": self.block_order, "rhs_lanes": self.rhs_lanes,
-                "nt_store": bool(self.flags & TUNE_NT_STORE)}
+                "nt_store": bool(self.flags & TUNE_NT_STORE), "cached_gauge": bool(self.flags & TUNE_CACHED_GAUGE)}
 
 
 class SolveInfo(ctypes.Structure):
@@ -263,8 +264,9 @@ def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torc
                                ws.handle, _stream_ptr(stream)))
 
 
-def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1, nt_store=False):
-    t = Tuning(int(nr_tile), int(block_order), int(rhs_lanes), TUNE_NT_STORE if nt_store else 0)
+def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1, nt_store=False, cached_gauge=False):
+    t = Tuning(int(nr_tile), int(block_order), int(rhs_lanes),
+               (TUNE_NT_STORE if nt_store else 0) | (TUNE_CACHED_GAUGE if cached_gauge else 0))
     _check(lib().lqcd_ws_set_tuning(ws.handle, prec, ctypes.byref(t)))
 
 
