@@ -302,3 +302,19 @@ def test_mixed_precision_stall_continues_in_fp64():
         assert rho <= 1e-10
         assert res.info[j]["fp64_from"] > 0
     assert res.status == lqcd.OK
+
+
+@pytest.mark.parametrize("inner", [lqcd.F64, lqcd.F32], ids=["f64", "f32"])
+def test_zero_source_column(inner):
+    """A batch whose second column is identically zero: that column is done at
+    setup with psi = 0 exactly, the others converge as usual."""
+    pm = lqcd.PM_F64 | lqcd.PM_F32
+    s = Setup((6, 4, 4, 6), P, TH_RND, 0.3, 0.1345, 1.9, 1.0, seed=12, pmask=pm)
+    eta = np.stack([inputs.gaussian_spinor(s.L, 1), np.zeros(s.lat.spinor_shape(), np.complex128),
+                    inputs.point_source(s.L, (1, 2, 3, 4), 2, 1)])
+    res = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, tol=1e-10, inner_prec=inner)
+    psi = res.psi.cpu().numpy()
+    assert res.status == lqcd.OK
+    assert np.all(psi[1] == 0) and res.info[1]["iters"] == 0 and res.info[1]["true_residual"] == 0.0
+    for j in (0, 2):
+        assert _oracle_rho(s, eta[j], psi[j]) <= 1e-10
