@@ -189,9 +189,11 @@ typedef struct lqcd_tuning {
                           output spinors with non-temporal stores;
                           LQCD_TUNE_CACHED_GAUGE: links and clover blocks
                           are read with ordinary (cached) loads instead of
-                          non-temporal ones */
+                          non-temporal ones; bits 2-3 (level << 
+                          LQCD_TUNE_OCC_SHIFT): at most 4, 3 or 2 resident
+                          workgroups per CU for level 1, 2, 3 (0: no cap) */
 } lqcd_tuning;
-enum { LQCD_TUNE_NT_STORE = 1, LQCD_TUNE_CACHED_GAUGE = 2 };
+enum { LQCD_TUNE_NT_STORE = 1, LQCD_TUNE_CACHED_GAUGE = 2, LQCD_TUNE_OCC_SHIFT = 2 };
 
 /* Hop-kernel configuration used by a workspace for precision `prec`
  * (default: nr_tile 1, block_order 1, rhs_lanes 1).  A launch over n rhs uses

@@ -372,6 +372,19 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
 
 static int sites_per_block(int rl) { return kHopBlock / (rl < 1 ? 1 : rl); }
 
+// Unused dynamic LDS that caps the workgroups resident per CU (160 KiB of LDS
+// per CU, plus each workgroup's small static reduction array): level 1 -> 4,
+// 2 -> 3, 3 -> 2 workgroups.  A smaller live set per XCD keeps more neighbour
+// spinors in L2 when every site carries many rhs.
+static unsigned lds_cap_bytes(int level) {
+  switch (level) {
+    case 1: return 39u << 10;
+    case 2: return 53u << 10;
+    case 3: return 63u << 10;
+    default: return 0u;
+  }
+}
+
 int hop_nblocks(const HopLaunch& h) {
   const int spb = sites_per_block(h.rhs_lanes);
   const int nb = (h.g.V2 + spb - 1) / spb;
@@ -391,6 +404,7 @@ static bool prepare(HopLaunch& h) {
   if (h.nr_tile < 1 || h.nr_tile > 4) return false;
   if (h.nrhs % (h.nr_tile * h.rhs_lanes) != 0) return false;
   h.nbs = hop_nblocks(h);
+  h.lds_cap = lds_cap_bytes(h.occ_cap);
   const int spb = sites_per_block(h.rhs_lanes);
   const long P = (long)h.g.Lxh * h.g.L[1];
   h.bpp = (int)(P / spb);
@@ -405,10 +419,10 @@ template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, in
 static hipError_t launch_rl(const HopLaunch& h, hipStream_t st) {
   const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
   switch (h.nr_tile) {
-    case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 4: k_hop<SG, SI, SO, PRE, POST, HOP, 4, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 4: k_hop<SG, SI, SO, PRE, POST, HOP, 4, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -436,10 +450,10 @@ template <typename SG, typename SI, typename SV, int RL>
 static hipError_t launch_xr_rl(const HopLaunch& h, hipStream_t st) {
   const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
   switch (h.nr_tile) {
-    case 1: k_hop_xr<SG, SI, SV, 1, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 2: k_hop_xr<SG, SI, SV, 2, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 3: k_hop_xr<SG, SI, SV, 3, RL><<<grid, kHopBlock, 0, st>>>(h); break;
-    case 4: k_hop_xr<SG, SI, SV, 4, RL><<<grid, kHopBlock, 0, st>>>(h); break;
+    case 1: k_hop_xr<SG, SI, SV, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 2: k_hop_xr<SG, SI, SV, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 3: k_hop_xr<SG, SI, SV, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 4: k_hop_xr<SG, SI, SV, 4, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -509,7 +509,7 @@ extern "C" int lqcd_ws_set_tuning(lqcd_ws_t* w, int prec, const lqcd_tuning* t) 
   if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: null pointer");
   if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: bad precision %d", prec);
   if (t->nr_tile < 1 || t->nr_tile > 4 || t->block_order < 0 || t->block_order > 4 ||
-      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE)))
+      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE | (3 << LQCD_TUNE_OCC_SHIFT))))
     return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: value out of range");
   w->tune[prec] = *t;
   return LQCD_OK;
@@ -544,6 +544,28 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   lqcd_tuning best_cfg = saved;
   OpCtx c{u, w, prec, nrhs, st};
   hipError_t err = hipSuccess;
+  // times the workspace's current tuning; keeps it if it is the fastest so far
+  auto trial = [&]() {
+    auto once = [&]() -> hipError_t {
+      hipError_t e = apply_hop_eo(c, w->m.X, w->m.R);
+      if (e == hipSuccess) e = apply_hop_oe(c, w->m.X, w->m.R, w->m.TMP, false, nullptr);
+      return e;
+    };
+    for (int i = 0; i < 2 && err == hipSuccess; ++i) err = once();
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    const int reps = 6;
+    for (int i = 0; i < reps && err == hipSuccess; ++i) err = once();
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    const double us = 1e3 * ms / reps;
+    if (err == hipSuccess && us < best_t) {
+      best_t = us;
+      best_cfg = w->tune[prec];
+    }
+  };
+  // pass 1: rhs lanes, rhs tile, block order, store and load kinds
   for (int rl = 1; rl <= 4 && err == hipSuccess; rl *= 2) {
     if (nrhs % rl || (prec == P_F64 && rl > 1)) continue;
     for (int nr = 1; nr <= 4 && err == hipSuccess; ++nr) {
@@ -552,26 +574,16 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
         const int order = cfg >> 2;
         const int flags = ((cfg & 1) ? LQCD_TUNE_NT_STORE : 0) | ((cfg & 2) ? LQCD_TUNE_CACHED_GAUGE : 0);
         w->tune[prec] = lqcd_tuning{nr, order, rl, flags};
-        auto once = [&]() -> hipError_t {
-          hipError_t e = apply_hop_eo(c, w->m.X, w->m.R);
-          if (e == hipSuccess) e = apply_hop_oe(c, w->m.X, w->m.R, w->m.TMP, false, nullptr);
-          return e;
-        };
-        for (int i = 0; i < 2 && err == hipSuccess; ++i) err = once();
-        if (err == hipSuccess) err = hipEventRecord(e0, st);
-        const int reps = 6;
-        for (int i = 0; i < reps && err == hipSuccess; ++i) err = once();
-        if (err == hipSuccess) err = hipEventRecord(e1, st);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        const double us = 1e3 * ms / reps;
-        if (err == hipSuccess && us < best_t) {
-          best_t = us;
-          best_cfg = w->tune[prec];
-        }
+        trial();
       }
     }
+  }
+  // pass 2: occupancy caps on the best configuration
+  const lqcd_tuning base = best_cfg;
+  for (int level = 1; level <= 3 && err == hipSuccess; ++level) {
+    w->tune[prec] = base;
+    w->tune[prec].flags = (base.flags & ~(3 << LQCD_TUNE_OCC_SHIFT)) | (level << LQCD_TUNE_OCC_SHIFT);
+    trial();
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -114,6 +114,7 @@ inline void apply_tuning(HopLaunch& h, const lqcd_tuning& t) {
   h.order = t.block_order;
   h.nt_out = (t.flags & LQCD_TUNE_NT_STORE) ? 1 : 0;
   h.cached_gauge = (t.flags & LQCD_TUNE_CACHED_GAUGE) ? 1 : 0;
+  h.occ_cap = (t.flags >> LQCD_TUNE_OCC_SHIFT) & 3;
 }
 inline void single_tile(HopLaunch& h) {
   h.nr_tile = 1;

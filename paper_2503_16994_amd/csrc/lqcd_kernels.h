@@ -58,6 +58,8 @@ struct HopLaunch {
   int nt_out;        // 1: non-temporal stores of the output spinor
   int cached_gauge;  // 1: ordinary (cached) loads of links and clover blocks
                      // instead of non-temporal ones (rhs tiles re-read them)
+  int occ_cap;       // 0..3: cap on resident workgroups per CU (unused LDS)
+  unsigned lds_cap;  // dynamic LDS bytes of the launch (set by the launcher)
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
   int bpp;  // site blocks per (z, t) plane

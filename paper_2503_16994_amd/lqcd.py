@@ -30,6 +30,7 @@ F64, F32, BF16 = 0, 1, 2
 PM_F64, PM_F32, PM_BF16 = 1, 2, 4
 TUNE_NT_STORE = 1  # lqcd_tuning.flags: non-temporal output stores in the hop kernels
 TUNE_CACHED_GAUGE = 2  # lqcd_tuning.flags: cached (not non-temporal) link and clover loads
+TUNE_OCC_SHIFT = 2  # lqcd_tuning.flags bits 2-3: cap of resident workgroups per CU (4, 3, 2)
 # operators
 (OP_DW, OP_DW_DAG, OP_G5DW, OP_DWDAGDW, OP_SCHUR, OP_SCHUR_DAG, OP_SCHUR_NORMAL, OP_HOP_EO,
  OP_HOP_OE) = range(9)
@@ -65,7 +66,8 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {"nr_tile": self.nr_tile, "block_order": self.block_order, "rhs_lanes": self.rhs_lanes,
-                "nt_store": bool(self.flags & TUNE_NT_STORE), "cached_gauge": bool(self.flags & TUNE_CACHED_GAUGE)}
+                "nt_store": bool(self.flags & TUNE_NT_STORE), "cached_gauge": bool(self.flags & TUNE_CACHED_GAUGE),
+                "occ_cap": (self.flags >> TUNE_OCC_SHIFT) & 3}
 
 
 class SolveInfo(ctypes.Structure):
@@ -264,9 +266,11 @@ def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torc
                                ws.handle, _stream_ptr(stream)))
 
 
-def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1, nt_store=False, cached_gauge=False):
+def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1, nt_store=False, cached_gauge=False,
+               occ_cap=0):
     t = Tuning(int(nr_tile), int(block_order), int(rhs_lanes),
-               (TUNE_NT_STORE if nt_store else 0) | (TUNE_CACHED_GAUGE if cached_gauge else 0))
+               (TUNE_NT_STORE if nt_store else 0) | (TUNE_CACHED_GAUGE if cached_gauge else 0)
+               | ((int(occ_cap) & 3) << TUNE_OCC_SHIFT))
     _check(lib().lqcd_ws_set_tuning(ws.handle, prec, ctypes.byref(t)))
 
 

@@ -250,15 +250,16 @@ def test_graph_capture_matches_eager_and_is_deterministic():
 
 
 def test_tuning_does_not_change_results():
-    """rhs tile, block order, rhs lanes, store and load kinds leave every rhs bitwise equal."""
+    """rhs tile, block order, rhs lanes, store and load kinds and occupancy caps
+    leave every rhs bitwise equal."""
     # 16x16x8x8: Lz % 8 == 0 and (Lx/2) Ly = 256, so block order 2 is exercised
     s = Setup((16, 16, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=8,
               pmask=lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16)
     eta = torch.from_numpy(np.stack([inputs.gaussian_spinor(s.L, k) for k in range(8)])).cuda()
     ref = {}
     for ip in (lqcd.F64, lqcd.F32, lqcd.BF16):
-        for cfg in ((1, 0, 1, False, False), (2, 1, 1, True, True), (3, 2, 2, False, True), (1, 3, 2, True, False),
-                    (1, 4, 4, False, False), (2, 2, 4, True, True)):
+        for cfg in ((1, 0, 1, False, False, 0), (2, 1, 1, True, True, 1), (3, 2, 2, False, True, 3),
+                    (1, 3, 2, True, False, 2), (1, 4, 4, False, False, 0), (2, 2, 4, True, True, 3)):
             ws = lqcd.Workspace(s.lat, s.gauge.pmask, 8)
             lqcd.set_tuning(ws, ip, *cfg)
             assert lqcd.get_tuning(ws, ip)["nr_tile"] == cfg[0]
