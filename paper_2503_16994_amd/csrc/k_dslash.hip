@@ -288,10 +288,35 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
   return true;
 }
 
+// alpha = rr / pAp for the rhs this workgroup owns (see HopLaunch::alpha_cg):
+// the same fixed-order sum as the stand-alone alpha kernel (thread-strided
+// partial sums, wavefront butterfly, the four waves in order)
+__device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
+  for (int r = blockIdx.x; r < a.nrhs; r += gridDim.x) {
+    CGState& c = a.alpha_cg[r];
+    if (c.done) continue;  // uniform over the workgroup
+    const double* p = a.alpha_parts + (size_t)r * a.alpha_nparts;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < a.alpha_nparts; i += kHopBlock) acc += p[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double v = sh[0] + sh[1] + sh[2] + sh[3];
+      c.pAp = v;
+      c.alpha = (v > 0.0) ? c.rr / v : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL>
 __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
-  __shared__ double red[(kHopBlock / 64) * RL];
+  __shared__ double red[(kHopBlock / 64) * RL > 4 ? (kHopBlock / 64) * RL : 4];
+  if (a.alpha_cg) fused_alpha(a, red);
   ThreadSite ts;
   cpx<A> v[NR][12];
   if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL>(a, ts, v)) return;

@@ -72,6 +72,12 @@ struct HopLaunch {
   long xr_rs;    // rhs stride of r and p
   long xr_xrs;   // rhs stride of x
   const struct CGState* cg;
+  // CG alpha fused into a hop launch that does not need it (k_hop only):
+  // alpha = rr / pAp with pAp the fixed-order sum of alpha_nparts partials per
+  // rhs; rhs r is handled by workgroup r mod grid, before its stencil work.
+  struct CGState* alpha_cg;   // nullptr: no alpha step
+  const double* alpha_parts;  // [nrhs][alpha_nparts]
+  int alpha_nparts;
 };
 
 int hop_nblocks(const HopLaunch& h);

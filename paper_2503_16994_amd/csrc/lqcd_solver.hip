@@ -84,9 +84,14 @@ HopLaunch mk(const Ctl& c, int lprec) {
   return h;
 }
 
-// out_o = A_oo^{-1} D_oe y_e = A_oo^{-1} (-1/2 H y_e)
-hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, int nr_tile) {
+// out_o = A_oo^{-1} D_oe y_e = A_oo^{-1} (-1/2 H y_e); with alpha_cg the
+// launch also computes the CG alpha of every rhs from alpha_parts
+hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, int nr_tile,
+                  CGState* alpha_cg = nullptr, const double* alpha_parts = nullptr, int alpha_nparts = 0) {
   HopLaunch h = mk(c, lprec);
+  h.alpha_cg = alpha_cg;
+  h.alpha_parts = alpha_parts;
+  h.alpha_nparts = alpha_nparts;
   h.p_out = 1;
   h.in_prec = y.prec;
   h.out_prec = out_o.prec;
@@ -376,8 +381,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   };
 
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
-  // eo: hop, hop (+g5, |Dhat p|^2), alpha, hop, hop fused with the x/r update
-  // (+|r|^2), beta, [reliable-update group], p update
+  // eo: hop, hop (+g5, |Dhat p|^2), hop (+alpha), hop fused with the x/r
+  // update (+|r|^2), beta, [reliable-update group], p update
   constexpr int kRuStride = 5;
   auto iteration = [&](int i) -> hipError_t {
     hipError_t e;
@@ -385,8 +390,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       const int nb_it = iter_parts(c, lprec);
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
-      if ((e = launch_cg_alpha(cg, parts, nb_it, N, st))) return e;
-      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile))) return e;
+      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
       if ((e = hop_oe_xr(c, lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
       if ((e = launch_cg_beta(cg, parts, nb_it, N, st))) return e;
     } else {
