@@ -51,12 +51,22 @@ struct WsLayout {
 
 // A captured chunk of solver iterations, valid for the workspace's lifetime
 // (its kernels read and write only the gauge field and workspace memory).
+// A captured chunk of CG iterations.  Its launches depend on the gauge
+// field, the solver, the precision of the recursion, the rhs count, the chunk
+// length and the hop-kernel tunings of that precision and of FP64 (reliable
+// updates); the workspace's buffers are fixed for its lifetime.
 struct GraphEntry {
   uint64_t gauge_uid;
   int solver, inner_prec, nrhs, chunk;
+  lqcd_tuning tune_inner, tune_f64;
   hipGraph_t graph;
   hipGraphExec_t exec;
 };
+
+inline bool same_tuning(const lqcd_tuning& a, const lqcd_tuning& b) {
+  return a.nr_tile == b.nr_tile && a.block_order == b.block_order && a.rhs_lanes == b.rhs_lanes &&
+         a.flags == b.flags;
+}
 
 struct lqcd_ws {
   const lqcd_geom_t* g;

@@ -418,7 +418,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       hipGraphExec_t exec = nullptr;
       for (auto& e : w->graphs)
         if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == key_prec && e.nrhs == N &&
-            e.chunk == K)
+            e.chunk == K && same_tuning(e.tune_inner, w->tune[key_prec]) && same_tuning(e.tune_f64, w->tune[P_F64]))
           exec = e.exec;
       if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -436,7 +436,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
           (void)hipGraphDestroy(gr);
           return hip_status(e3, "hipGraphInstantiate");
         }
-        w->graphs.push_back(GraphEntry{u->uid, prm->solver, key_prec, N, K, gr, exec});
+        w->graphs.push_back(GraphEntry{u->uid, prm->solver, key_prec, N, K, w->tune[key_prec], w->tune[P_F64], gr, exec});
       }
       LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;
