@@ -21,11 +21,13 @@ The JSON line (stdout) also carries
   precision;
 * "roofline": the dominant kernel of the step (the FP64 odd->even hop with
   the clover block), algorithmic bytes per launch / average launch time
-  (HIP events on its stream);
+  (100 launches replayed from one graph, HIP events on its stream);
 * "dw_hbm": the hop kernels at 32^3x64 (working set > 1 GB, beyond the 256 MB
   last-level cache) in FP64/FP32/BF16;
 * "serving": a Poisson stream of mixed propagator requests through the
-  serving loop, p50/p99 latency and solves/s;
+  serving loop, p50/p99 latency and solves/s (with --serve-full also a run at
+  0.7x the measured capacity, where the latencies describe the service and
+  not a growing backlog);
 * "cpu_baseline": the FP64 CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-hbm] [--no-cpu]
@@ -52,7 +54,12 @@ REALS_HOP_OE = 144   # U 72 + psi_o 12 + psi_e 12 + A_ee 36 + out 12
 REALS_HOP_EO = 132   # U 72 + psi_e 12 + A_oo^-1 36 + out 12
 BYTES_PER_REAL = {0: 8, 1: 4, 2: 2}
 DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1,1>"
-ROOFLINE_TUNING = (1, 2, 1, True)  # nr_tile, block_order, rhs_lanes, nt_store
+# hop tuning of the benchmark step and of its roofline measurement: what the
+# autotuner picks at 16^3x32 (nr_tile, block_order, rhs_lanes, nt_store,
+# cached_gauge, occ_cap); cached gauge loads keep links and clover in the
+# last-level cache, which holds this lattice's whole working set
+STEP_TUNING = (1, 1, 1, True, True, 0)
+ROOFLINE_LAUNCHES = 100
 KERNEL_SOURCES = ["paper_2503_16994_amd/csrc/k_dslash.hip", "paper_2503_16994_amd/csrc/lqcd_dev.h"]
 
 
@@ -68,9 +75,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(name):
+def stored_traffic(name, tuning=None):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source in the same tuning."""
     path = os.path.join(ROOT, "profiles", "hop_oe_fp64_16x16x16x32_counters.json")
     try:
         with open(path) as f:
@@ -78,6 +85,8 @@ def stored_traffic(name):
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != name:
+        return None
+    if tuning is not None and d.get("tuning") != tuning:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -120,13 +129,13 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-full", action="store_true",
-                    help="serving as specified: 400 requests, then a run at 0.7x the measured capacity")
+                    help="longer serving run: 60 requests at the offered rate, then 20 at 0.7x the measured capacity")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only calibration copy/sum and hop-kernel launches (profiler runs)")
     args = ap.parse_args()
     if args.serve_full and args.serve_requests == 16:
-        args.serve_requests = 400
+        args.serve_requests = 60
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent propagators shard across GPUs with no communication; see DESIGN.md)",
@@ -154,7 +163,8 @@ def main():
     ws1 = lqcd.Workspace(lat, pm, 1)
     ws12 = lqcd.Workspace(lat, pm, 12)
     d = lqcd.dirac(KAPPA, CSW)
-    tune64, _ = lqcd.autotune(gauge, d, lqcd.F64, 1, ws1, stream=stream)
+    lqcd.set_tuning(ws1, lqcd.F64, *STEP_TUNING)
+    tune64 = lqcd.get_tuning(ws1, lqcd.F64)
     torch.cuda.synchronize()
 
     def step():
@@ -180,19 +190,34 @@ def main():
     vin = (torch.randn(vb // 8, device="cuda", dtype=torch.float64)).view(torch.uint8)
     vout = torch.empty(vb, dtype=torch.uint8, device="cuda")
 
-    # the configuration of the committed counter summary (block order 2, which
-    # this lattice turns into 1, and non-temporal output stores)
-    lqcd.set_tuning(ws1, lqcd.F64, *ROOFLINE_TUNING)
-    tune_roof = lqcd.get_tuning(ws1, lqcd.F64)
+    tune_roof = lqcd.get_tuning(ws1, lqcd.F64)  # the step's configuration
 
     def hop_oe():
         lqcd.dw_apply_internal(gauge, d, vin, vout, lqcd.OP_HOP_OE, lqcd.F64, 1, ws1, stream=stream)
 
-    ms_oe = time_launches(hop_oe, 100, stream)
+    # 100 launches captured in one graph: at this size a launch (~25 us) is
+    # shorter than a call through Python, so eager launches would time the host
+    for _ in range(3):
+        hop_oe()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for _ in range(ROOFLINE_LAUNCHES):
+            hop_oe()
+    graph.replay()
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    graph.replay()
+    e1.record(stream)
+    e1.synchronize()
+    ms_oe = e0.elapsed_time(e1) / ROOFLINE_LAUNCHES
+    del graph
     alg_bytes = REALS_HOP_OE * BYTES_PER_REAL[0] * lat.volume
     achieved = alg_bytes / (ms_oe * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(DOMINANT_KERNEL),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(DOMINANT_KERNEL, tune_roof),
                 "kernel": DOMINANT_KERNEL, "avg_launch_us": round(ms_oe * 1e3, 2),
                 "alg_bytes_per_launch": alg_bytes, "tuning": tune_roof,
                 "note": "16^3x32 working set (~150 MB) fits the 256 MB last-level cache; "
@@ -244,7 +269,7 @@ def main():
         serving = {"offered": serve_leg(args.serve_requests, args.serve_rate, U2)}
         if args.serve_full:
             cap = serving["offered"]["requests_per_s"]
-            serving["at_0.7_capacity"] = serve_leg(max(20, args.serve_requests // 8), 0.7 * cap, U2, seed=98)
+            serving["at_0.7_capacity"] = serve_leg(20, 0.7 * cap, U2, seed=98)
 
     # ---- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
@@ -453,6 +478,9 @@ def serve_leg(n_requests, rate, U16, seed=99):
                 r = srv.poll(t)
                 if r is not None:
                     done[t] = r
+                    if len(done) % 10 == 0:
+                        log(f"serving: {len(done)}/{len(tickets)} requests done "
+                            f"({time.perf_counter() - t0:.1f} s)")
         time.sleep(0.001)
     wall = time.perf_counter() - t0
     lat_s = np.array([done[t][2][2] - done[t][2][0] for t in tickets])
@@ -478,8 +506,8 @@ def profile_kernels(stream):
     calibrate FETCH_SIZE/WRITE_SIZE against known bytes, and the copy rate), a
     1 GiB read-only sum (read rate), then 20 launches of each hop kernel:
     FP64 at 16^3x32 and at 32^3x64, FP32 and BF16 at 32^3x64 (one rhs), and
-    FP32 with 12 rhs at 32^3x64 (rhs tile 3), all with block order 2 (order 1
-    where the lattice does not allow 2) and non-temporal output stores."""
+    FP32 with 12 rhs at 32^3x64 (rhs tile 3); at 16^3x32 in the benchmark
+    step's tuning, at 32^3x64 with block order 2 and non-temporal stores."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -504,7 +532,7 @@ def profile_kernels(stream):
         ws = lqcd.Workspace(lat, pm if big else lqcd.PM_F64, nr)
         d = lqcd.dirac(KAPPA, CSW)
         # (nr_tile, block_order, rhs_lanes, nt_store): what the autotuner picks
-        cases = [(lqcd.F64, 1, ROOFLINE_TUNING)]
+        cases = [(lqcd.F64, 1, STEP_TUNING if not big else (1, 2, 1, True))]
         if big:
             cases += [(lqcd.F32, 1, (1, 2, 1, True)), (lqcd.BF16, 1, (1, 2, 1, True)), (lqcd.F32, 12, (3, 2, 1, True))]
         for prec, nrhs, tune in cases:
