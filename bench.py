@@ -105,6 +105,31 @@ def time_launches(fn, reps, stream):
     return e0.elapsed_time(e1) / reps  # ms
 
 
+def hop_rates(g, lat_, ws, d, prec, nrhs, stream, reps=30):
+    """Average launch time and algorithmic GB/s of the two hop kernels (and,
+    for one FP64 rhs, of the full-lattice Dw) on random internal vectors."""
+    import torch
+
+    from paper_2503_16994_amd import lqcd
+    vb = lqcd.vec_bytes(lat_, prec, nrhs, 2)
+    if prec == lqcd.BF16:  # finite bf16 pairs
+        x = torch.randn(vb // 2, device="cuda").to(torch.bfloat16).view(torch.uint8)
+    else:
+        x = torch.randn(vb // 4, device="cuda").view(torch.uint8)
+    y = torch.empty(vb, dtype=torch.uint8, device="cuda")
+    ops = [(lqcd.OP_HOP_EO, "hop_eo", 108 + 24 * nrhs), (lqcd.OP_HOP_OE, "hop_oe", 108 + 36 * nrhs)]
+    if prec == lqcd.F64 and nrhs == 1:
+        ops.append((lqcd.OP_DW, "dw_full", 192))  # psi 24 + U 72 + A 72 + out 24
+    out = {}
+    for op, name, reals in ops:
+        ms = time_launches(lambda op=op: lqcd.dw_apply_internal(g, d, x, y, op, prec, nrhs, ws, stream=stream),
+                           reps, stream)
+        gbs = reals * BYTES_PER_REAL[prec] * lat_.volume / (ms * 1e-3) / 1e9
+        out[name] = {"us": round(ms * 1e3, 1), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del x, y
+    return out
+
+
 def timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -226,13 +251,18 @@ def main():
     del vin, vout
 
     # ---- mixed precision, 12 rhs in one solve ---------------------------------
-    def mixed_leg(g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag, precs=("f64", "f32", "bf16")):
-        """12 rhs in one solve per inner precision (autotuned kernels)."""
+    def mixed_leg(g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag, precs=("f64", "f32", "bf16"),
+                  hbm=None):
+        """12 rhs in one solve per inner precision (autotuned kernels); with a
+        dict `hbm`, also the 12-rhs hop-kernel rates in each precision."""
         res = {}
         pmap = {"f64": lqcd.F64, "f32": lqcd.F32, "bf16": lqcd.BF16}
         for name in precs:
             ip = pmap[name]
             tune, _ = lqcd.autotune(g, lqcd.dirac(kappa, csw), ip, 12, ws, stream=stream)
+            if hbm is not None:
+                for k, v in hop_rates(g, lat_, ws, lqcd.dirac(kappa, csw), ip, 12, stream).items():
+                    hbm[f"{k}_{name}_12rhs"] = dict(v, tuning=tune)
 
             def mstep():
                 return lqcd.solve(g, etas, kappa, csw, tol=TOL, solver=lqcd.SOLVER_CG_EO, inner_prec=ip,
@@ -345,20 +375,8 @@ def c3_leg(stream, pm, no_mixed, mixed_leg):
     dw_hbm = {"lattice": list(L3)}
     for prec, pname in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.BF16, "bf16")):
         tune, _ = lqcd.autotune(g3, d3, prec, 1, ws3, stream=stream)
-        vb3 = lqcd.vec_bytes(lat3, prec, 1, 2)
-        if prec == lqcd.BF16:  # finite bf16 pairs
-            x3 = torch.randn(vb3 // 2, device="cuda").to(torch.bfloat16).view(torch.uint8)
-        else:
-            x3 = torch.randn(vb3 // 4, device="cuda").view(torch.uint8)
-        y3 = torch.empty(vb3, dtype=torch.uint8, device="cuda")
-        for op, oname, reals in ((lqcd.OP_HOP_EO, "hop_eo", REALS_HOP_EO), (lqcd.OP_HOP_OE, "hop_oe", REALS_HOP_OE)):
-            f = (lambda op=op, prec=prec, x3=x3, y3=y3:
-                 lqcd.dw_apply_internal(g3, d3, x3, y3, op, prec, 1, ws3, stream=stream))
-            ms = time_launches(f, 50, stream)
-            gbs = reals * BYTES_PER_REAL[prec] * lat3.volume / (ms * 1e-3) / 1e9
-            dw_hbm[f"{oname}_{pname}"] = {"us": round(ms * 1e3, 1), "GB/s": round(gbs, 1),
-                                         "frac": round(gbs / HBM_PEAK_GBS, 4), "tuning": tune}
-        del x3, y3
+        for k, v in hop_rates(g3, lat3, ws3, d3, prec, 1, stream).items():
+            dw_hbm[f"{k}_{pname}"] = dict(v, tuning=tune)
     log(f"dw_hbm: {dw_hbm}")
     c3 = {"lattice": list(L3), "kappa": kappa, "csw": CSW, "source": "Z2 complex noise"}
     eta3 = torch.from_numpy(inputs.z2_noise(L3, seed=3)).cuda()
@@ -391,7 +409,9 @@ def c3_leg(stream, pm, no_mixed, mixed_leg):
     torch.cuda.empty_cache()
     if not no_mixed:
         ws12 = lqcd.Workspace(lat3, pm, 12)
-        c3["propagator_12"]["multi_rhs_12"] = mixed_leg(g3, lat3, ws12, etap, kappa, CSW, fp64, 1, 1, "32^3x64")
+        c3["propagator_12"]["multi_rhs_12"] = mixed_leg(g3, lat3, ws12, etap, kappa, CSW, fp64, 1, 1, "32^3x64",
+                                                        hbm=dw_hbm)
+        log(f"dw_hbm with 12 rhs: { {k: v for k, v in dw_hbm.items() if k.endswith('12rhs')} }")
         del ws12
     log(f"C3 propagator: {c3['propagator_12']}")
     del g3, etap

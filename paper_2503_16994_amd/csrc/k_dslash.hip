@@ -2,7 +2,9 @@
 //
 // Work decomposition.  A thread owns one output site of parity p_out and NR
 // right-hand sides; RL consecutive lanes share one site and own RL different
-// rhs groups (so a 256-thread block covers 256/RL sites and RL*NR rhs).  Per
+// rhs groups (so a 128-thread workgroup covers 128/RL sites and RL*NR rhs;
+// 128 rather than 256 threads gives the one-rhs launches on a 16^3x32 lattice
+// two workgroups per CU instead of one).  Per
 // hop a thread loads the link (9 site-coalesced complex loads; the RL lanes of
 // a site issue identical addresses, which the memory pipeline serves once)
 // and, for each of its NR rhs, the neighbour spinor (12 loads), spin-projects
@@ -24,7 +26,7 @@
 
 namespace lqcd {
 
-constexpr int kHopBlock = 256;
+constexpr int kHopBlock = 128;  // threads per workgroup
 
 template <int MU, int DIR, int NR, typename A, typename SG, typename SI>
 __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, const SI* yb, int p,
@@ -289,8 +291,8 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 }
 
 // alpha = rr / pAp for the rhs this workgroup owns (see HopLaunch::alpha_cg):
-// the same fixed-order sum as the stand-alone alpha kernel (thread-strided
-// partial sums, wavefront butterfly, the four waves in order)
+// a fixed-order sum (thread-strided partial sums, wavefront butterfly, the
+// waves in order)
 __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
   for (int r = blockIdx.x; r < a.nrhs; r += gridDim.x) {
     CGState& c = a.alpha_cg[r];
@@ -304,7 +306,8 @@ __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const double v = sh[0] + sh[1] + sh[2] + sh[3];
+      double v = 0.0;
+      for (int w = 0; w < kHopBlock / 64; ++w) v += sh[w];  // waves in order
       c.pAp = v;
       c.alpha = (v > 0.0) ? c.rr / v : 0.0;
     }

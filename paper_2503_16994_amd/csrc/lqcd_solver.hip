@@ -293,7 +293,10 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   CGState* cg = m.cg;
   const int* done = &cg[0].done;
   const int* skip_ru = &cg[0].skip_ru;
-  const int nb_hop = (int)((g->V2 + 255) / 256);  // site blocks of an FP64 hop launch
+  // partials per rhs of an FP64 single-tile hop launch (setup and reliable updates)
+  HopLaunch h1 = mk(c, P_F64);
+  single_tile(h1);
+  const int nb_hop = hop_nparts(h1);
 
   LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
   LQCD_HIP(launch_fill_zero(m.X, full_bytes, st));

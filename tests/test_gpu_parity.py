@@ -28,7 +28,8 @@ TH_RND = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.7])))
 TH_SPATIAL = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.0])))
 
 # (L, bc, theta, eps, kappa, csw, cF); the 6x4x4x6 lattice has V/2 = 288 sites,
-# i.e. one full and one ragged block of 256 threads.
+# i.e. two full 128-thread workgroups and a ragged one (and a ragged 64-site
+# layout tile).
 OP_CASES = [
     ((4, 4, 4, 4), P, TH_AP, 0.3, 0.12, 1.0, 1.0),
     ((6, 4, 4, 6), P, TH_RND, 0.3, 0.1345, 1.9, 1.0),
