@@ -434,6 +434,7 @@ def ctx_leg(stream):
     del U
     ws = lqcd.Workspace(lat, lqcd.PM_F64, 1)
     eta = torch.from_numpy(inputs.point_source(L)[None]).cuda()
+    lqcd.autotune(g, lqcd.dirac(KAPPA, CSW), lqcd.F64, 1, ws, stream=stream)
 
     def run():
         return lqcd.solve(g, eta, KAPPA, CSW, tol=1e-30, solver=lqcd.SOLVER_CG_FULL, maxiter=1000,

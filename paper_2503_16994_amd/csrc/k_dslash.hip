@@ -106,18 +106,20 @@ __device__ inline void load_block(const SG* C, int blk, int s, bool cached, cpx<
 //   order 4: as 2, with the rhs tile outermost.
 // Tile-inner orders read each link once for all tiles but need a reuse window
 // holding all rhs; tile-outer orders read the links once per tile and keep
-// the reuse window of a single tile.
-__device__ inline void block_order(const HopLaunch& a, int b, int nb, int ntiles, int& sb, int& tile) {
+// the reuse window of a single tile.  A launch over both parities is two
+// halves of the grid, each mapped like a one-parity launch (nb and nbs per
+// half).
+__device__ inline void block_order(const HopLaunch& a, int b, int nb, int nbs, int ntiles, int& sb, int& tile) {
   if (a.order == 0) {
-    sb = b % a.nbs;
-    tile = b / a.nbs;
+    sb = b % nbs;
+    tile = b / nbs;
     return;
   }
   const int x = b & 7, j = b >> 3;
   if (a.order == 3) {
     const int l = xcd_remap(b, nb);
-    tile = l / a.nbs;
-    sb = l % a.nbs;
+    tile = l / nbs;
+    sb = l % nbs;
     return;
   }
   if (a.order == 2 || a.order == 4) {
@@ -127,7 +129,7 @@ __device__ inline void block_order(const HopLaunch& a, int b, int nb, int ntiles
       tile = j % ntiles;
       q = j / ntiles;
     } else {
-      const int per_tile = a.nbs >> 3;  // site blocks per XCD and tile
+      const int per_tile = nbs >> 3;  // site blocks per XCD and tile
       tile = j / per_tile;
       q = j % per_tile;
     }
@@ -173,8 +175,16 @@ template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL,
 __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v)[NR][12]) {
   constexpr int SPB = kHopBlock / RL;  // sites per block
   const KGeom& g = a.g;
-  int tile;
-  block_order(a, blockIdx.x, gridDim.x, a.nrhs / (NR * RL), ts.sb, tile);
+  int tile, p = a.p_out, b = blockIdx.x, nb = gridDim.x, nbs = a.nbs;
+  if (a.both) {  // parity 0 in the first half of the grid, parity 1 in the second
+    nb >>= 1;
+    nbs >>= 1;
+    p = (b >= nb) ? 1 : 0;
+    b -= p * nb;
+  }
+  int bx;  // site block within the parity
+  block_order(a, b, nb, nbs, a.nrhs / (NR * RL), bx, tile);
+  ts.sb = p * nbs + bx;  // partial-sum slot
   const int lane_r = (RL > 1) ? (int)(threadIdx.x % RL) : 0;
   ts.rhs_tile0 = tile * NR * RL;
   ts.rhs0 = ts.rhs_tile0 + lane_r * NR;  // this lane's first rhs
@@ -183,12 +193,6 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
     for (int r = 0; r < NR * RL; ++r)
       all = all && (a.done[(ts.rhs_tile0 + r) * (int)(sizeof(CGState) / sizeof(int))] != 0);
     if (all) return false;
-  }
-  int p = a.p_out, bx = ts.sb;
-  if (a.both) {
-    const int nbh = a.nbs >> 1;
-    p = (bx >= nbh) ? 1 : 0;
-    bx -= p * nbh;
   }
   ts.p = p;
   const int s = bx * SPB + (int)(threadIdx.x / RL);
@@ -436,7 +440,7 @@ static bool prepare(HopLaunch& h) {
   const int spb = sites_per_block(h.rhs_lanes);
   const long P = (long)h.g.Lxh * h.g.L[1];
   h.bpp = (int)(P / spb);
-  const bool slab_ok = !h.both && (h.g.L[2] % 8) == 0 && (P % spb) == 0;
+  const bool slab_ok = (h.g.L[2] % 8) == 0 && (P % spb) == 0;
   if (h.order == 2 && !slab_ok) h.order = 1;
   if (h.order == 4 && !slab_ok) h.order = 3;
   if (h.order < 0 || h.order > 4) h.order = 1;
