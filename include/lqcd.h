@@ -176,13 +176,16 @@ size_t lqcd_vec_bytes(const lqcd_geom_t *g, int prec, int nrhs, int nparity);
 
 /* ---- kernel tuning (autotuner) ------------------------------------------ */
 typedef struct lqcd_tuning {
-  int32_t nr_tile;     /* right-hand sides per thread in the hop kernels: 1..4 */
+  int32_t nr_tile;     /* right-hand sides per thread in the hop kernels: 1..3
+                          (a fourth needs more registers than a lane has) */
   int32_t block_order; /* workgroup -> sites: 0 plain; 1 every XCD walks a
                           contiguous range; 2 every XCD owns a z-slab and walks
                           it plane by plane in t (needs Lz % 8 == 0 and a
                           whole number of workgroups per (z, t) plane, else 1
                           is used); 3 and 4 as 1 and 2 with the rhs tiles one
-                          after the other */
+                          after the other; 5 and 6 as 2 with slabs of 1 or 2
+                          planes swept in several passes (6 needs
+                          Lz % 16 == 0) */
   int32_t rhs_lanes;   /* lanes sharing one site, each with its own nr_tile
                           rhs: 1, 2 or 4 (FP64 uses 1) */
   int32_t flags;       /* LQCD_TUNE_NT_STORE: the hop kernels write their

@@ -103,7 +103,13 @@ __device__ inline void load_block(const SG* C, int blk, int s, bool cached, cpx<
 //            Lz % 8 == 0 and a whole number of site blocks per (z, t) plane
 //            (else order 1).
 //   order 3: as 1, with the rhs tile outermost (the whole lattice per tile);
-//   order 4: as 2, with the rhs tile outermost.
+//   order 4: as 2, with the rhs tile outermost;
+//   orders 5, 6: as 2 with slabs of 1 or 2 planes: XCD x sweeps t over the
+//            planes z = d (x + 8 k) .. d (x + 8 k) + d - 1 for pass k = 0, 1,
+//            ... (d = 1 or 2); a t-step then holds d/(Lz/8) of the data of
+//            order 2, so the t-neighbours stay in L2 with many rhs per site,
+//            at the price of z-neighbours in another XCD's L2 (6 requires
+//            Lz % 16 == 0).
 // Tile-inner orders read each link once for all tiles but need a reuse window
 // holding all rhs; tile-outer orders read the links once per tile and keep
 // the reuse window of a single tile.  A launch over both parities is two
@@ -122,10 +128,11 @@ __device__ inline void block_order(const HopLaunch& a, int b, int nb, int nbs, i
     sb = l % nbs;
     return;
   }
-  if (a.order == 2 || a.order == 4) {
-    const int bpp = a.bpp, zs = a.g.L[2] >> 3;
+  if (a.order == 2 || a.order >= 4) {
+    const int bpp = a.bpp, Lz = a.g.L[2];
+    const int depth = (a.order == 5) ? 1 : (a.order == 6 ? 2 : (Lz >> 3));  // planes per slab
     int q;
-    if (a.order == 2) {
+    if (a.order != 4) {
       tile = j % ntiles;
       q = j / ntiles;
     } else {
@@ -135,9 +142,11 @@ __device__ inline void block_order(const HopLaunch& a, int b, int nb, int nbs, i
     }
     const int pb = q % bpp;
     q /= bpp;
-    const int zl = q % zs;
-    const int t = q / zs;
-    sb = pb + bpp * (x * zs + zl + a.g.L[2] * t);
+    const int zl = q % depth;
+    q /= depth;
+    const int t = q % a.g.L[3];
+    const int pass = q / a.g.L[3];  // 0 unless depth < Lz / 8
+    sb = pb + bpp * (depth * (x + 8 * pass) + zl + Lz * t);
     return;
   }
   const int l = xcd_remap(b, nb);
@@ -433,7 +442,7 @@ int hop_nparts(const HopLaunch& h0) {
 // fill in nbs/bpp and validate the block order for this launch
 static bool prepare(HopLaunch& h) {
   if (h.rhs_lanes != 1 && h.rhs_lanes != 2 && h.rhs_lanes != 4) return false;
-  if (h.nr_tile < 1 || h.nr_tile > 4) return false;
+  if (h.nr_tile < 1 || h.nr_tile > 3) return false;
   if (h.nrhs % (h.nr_tile * h.rhs_lanes) != 0) return false;
   h.nbs = hop_nblocks(h);
   h.lds_cap = lds_cap_bytes(h.occ_cap);
@@ -441,9 +450,10 @@ static bool prepare(HopLaunch& h) {
   const long P = (long)h.g.Lxh * h.g.L[1];
   h.bpp = (int)(P / spb);
   const bool slab_ok = (h.g.L[2] % 8) == 0 && (P % spb) == 0;
-  if (h.order == 2 && !slab_ok) h.order = 1;
+  if ((h.order == 2 || h.order == 5) && !slab_ok) h.order = 1;
+  if (h.order == 6 && !(slab_ok && (h.g.L[2] % 16) == 0)) h.order = 1;
   if (h.order == 4 && !slab_ok) h.order = 3;
-  if (h.order < 0 || h.order > 4) h.order = 1;
+  if (h.order < 0 || h.order > 6) h.order = 1;
   return true;
 }
 
@@ -454,7 +464,6 @@ static hipError_t launch_rl(const HopLaunch& h, hipStream_t st) {
     case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 4: k_hop<SG, SI, SO, PRE, POST, HOP, 4, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -485,7 +494,6 @@ static hipError_t launch_xr_rl(const HopLaunch& h, hipStream_t st) {
     case 1: k_hop_xr<SG, SI, SV, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     case 2: k_hop_xr<SG, SI, SV, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     case 3: k_hop_xr<SG, SI, SV, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 4: k_hop_xr<SG, SI, SV, 4, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

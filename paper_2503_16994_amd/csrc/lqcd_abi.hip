@@ -508,7 +508,7 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
 extern "C" int lqcd_ws_set_tuning(lqcd_ws_t* w, int prec, const lqcd_tuning* t) {
   if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: null pointer");
   if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: bad precision %d", prec);
-  if (t->nr_tile < 1 || t->nr_tile > 4 || t->block_order < 0 || t->block_order > 4 ||
+  if (t->nr_tile < 1 || t->nr_tile > 3 || t->block_order < 0 || t->block_order > 6 ||
       (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE | (3 << LQCD_TUNE_OCC_SHIFT))))
     return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: value out of range");
   w->tune[prec] = *t;
@@ -568,9 +568,9 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   // pass 1: rhs lanes, rhs tile, block order, store and load kinds
   for (int rl = 1; rl <= 4 && err == hipSuccess; rl *= 2) {
     if (nrhs % rl || (prec == P_F64 && rl > 1)) continue;
-    for (int nr = 1; nr <= 4 && err == hipSuccess; ++nr) {
+    for (int nr = 1; nr <= 3 && err == hipSuccess; ++nr) {
       if (nrhs % (nr * rl)) continue;
-      for (int cfg = 0; cfg < 20 && err == hipSuccess; ++cfg) {
+      for (int cfg = 0; cfg < 28 && err == hipSuccess; ++cfg) {
         const int order = cfg >> 2;
         const int flags = ((cfg & 1) ? LQCD_TUNE_NT_STORE : 0) | ((cfg & 2) ? LQCD_TUNE_CACHED_GAUGE : 0);
         w->tune[prec] = lqcd_tuning{nr, order, rl, flags};

@@ -116,7 +116,7 @@ struct HopSpec {
 // with nr_tile rhs; both are reduced until their product divides nrhs
 inline void apply_tuning(HopLaunch& h, const lqcd_tuning& t) {
   int rl = (t.rhs_lanes == 2 || t.rhs_lanes == 4) ? t.rhs_lanes : 1;
-  int nr = t.nr_tile < 1 ? 1 : (t.nr_tile > 4 ? 4 : t.nr_tile);
+  int nr = t.nr_tile < 1 ? 1 : (t.nr_tile > 3 ? 3 : t.nr_tile);
   while (h.nrhs % rl) rl >>= 1;
   while (h.nrhs % (nr * rl)) --nr;
   h.nr_tile = nr;

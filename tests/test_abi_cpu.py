@@ -120,7 +120,7 @@ def test_tuning_values_are_validated():
     assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK
     assert back.as_dict() == {"nr_tile": 2, "block_order": 4, "rhs_lanes": 2, "nt_store": True, "cached_gauge": False,
                               "occ_cap": 0}
-    for bad in (lqcd.Tuning(5, 1, 1, 0), lqcd.Tuning(1, 5, 1, 0), lqcd.Tuning(1, 1, 3, 0), lqcd.Tuning(1, 1, 1, 16)):
+    for bad in (lqcd.Tuning(4, 1, 1, 0), lqcd.Tuning(1, 7, 1, 0), lqcd.Tuning(1, 1, 3, 0), lqcd.Tuning(1, 1, 1, 16)):
         assert lib.lqcd_ws_set_tuning(w, lqcd.F32, ctypes.byref(bad)) == lqcd.EINVAL
     assert lib.lqcd_ws_set_tuning(w, 3, ctypes.byref(ok)) == lqcd.EINVAL
     assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK and back.flags == lqcd.TUNE_NT_STORE

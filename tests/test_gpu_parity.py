@@ -259,14 +259,16 @@ def test_graph_capture_matches_eager_and_is_deterministic():
 def test_tuning_does_not_change_results():
     """rhs tile, block order, rhs lanes, store and load kinds and occupancy caps
     leave every rhs bitwise equal."""
-    # 16x16x8x8: Lz % 8 == 0 and (Lx/2) Ly = 256, so block order 2 is exercised
+    # 16x16x8x8: Lz % 8 == 0 and (Lx/2) Ly = 128, so block orders 2 and 5 are
+    # exercised (6 needs Lz % 16 == 0 and falls back to 1 here)
     s = Setup((16, 16, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=8,
               pmask=lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16)
     eta = torch.from_numpy(np.stack([inputs.gaussian_spinor(s.L, k) for k in range(8)])).cuda()
     ref = {}
     for ip in (lqcd.F64, lqcd.F32, lqcd.BF16):
         for cfg in ((1, 0, 1, False, False, 0), (2, 1, 1, True, True, 1), (3, 2, 2, False, True, 3),
-                    (1, 3, 2, True, False, 2), (1, 4, 4, False, False, 0), (2, 2, 4, True, True, 3)):
+                    (1, 3, 2, True, False, 2), (1, 4, 4, False, False, 0), (2, 5, 4, True, True, 3),
+                    (3, 6, 1, True, False, 0)):
             ws = lqcd.Workspace(s.lat, s.gauge.pmask, 8)
             lqcd.set_tuning(ws, ip, *cfg)
             assert lqcd.get_tuning(ws, ip)["nr_tile"] == cfg[0]
@@ -284,7 +286,7 @@ def test_autotune_picks_a_valid_config():
     ws = lqcd.Workspace(s.lat, s.gauge.pmask, 12)
     best, us = lqcd.autotune(s.gauge, s.d, lqcd.F32, 12, ws)
     print("autotune 8^3x16 F32 N=12:", best, f"{us:.1f} us")
-    assert best["nr_tile"] in (1, 2, 3, 4) and us > 0
+    assert best["nr_tile"] in (1, 2, 3) and us > 0
     assert lqcd.get_tuning(ws, lqcd.F32) == best
     eta = torch.from_numpy(inputs.point_sources_12(s.L)).cuda()
     r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=lqcd.F32, ws=ws)
