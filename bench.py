@@ -163,7 +163,7 @@ def main():
         args.serve_requests = 60
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent propagators shard across GPUs with no communication; see DESIGN.md)",
+              "(independent propagators shard across GPUs with no communication between them)",
               file=sys.stderr)
         sys.exit(2)
 
