@@ -426,6 +426,14 @@ static unsigned lds_cap_bytes(int level) {
   }
 }
 
+// most partial sums per rhs any hop launch writes on V2 sites per parity:
+// 4 rhs lanes (fewest sites per workgroup), or both parities with one lane
+int hop_max_parts(long V2) {
+  const long one = (V2 + sites_per_block(4) - 1) / sites_per_block(4);
+  const long both = 2 * ((V2 + sites_per_block(1) - 1) / sites_per_block(1));
+  return (int)(one > both ? one : both);
+}
+
 int hop_nblocks(const HopLaunch& h) {
   const int spb = sites_per_block(h.rhs_lanes);
   const int nb = (h.g.V2 + spb - 1) / spb;

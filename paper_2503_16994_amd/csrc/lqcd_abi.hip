@@ -213,7 +213,7 @@ WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base) {
     m.qb = (bf16x2*)take(half16);
     m.tb = (bf16x2*)take(half16);
   }
-  const int hop_parts = 2 * (int)((g->V2 + 63) / 64);  // up to 4 rhs lanes per site
+  const int hop_parts = hop_max_parts(g->V2);
   m.max_parts = hop_parts > 2048 ? hop_parts : 2048;
   m.partials = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));
   m.partials2 = (double*)take((size_t)nrhs * m.max_parts * sizeof(double));

@@ -81,6 +81,7 @@ struct HopLaunch {
 };
 
 int hop_nblocks(const HopLaunch& h);
+int hop_max_parts(long V2);  // bound on partials per rhs of any hop launch
 int hop_nparts(const HopLaunch& h);  // partials per rhs of a tiled hop launch
 hipError_t launch_hop(const HopLaunch& h, hipStream_t st);
 hipError_t launch_hop_xr(const HopLaunch& h, hipStream_t st);
