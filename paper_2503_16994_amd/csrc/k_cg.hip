@@ -96,16 +96,15 @@ __global__ void k_cg_alpha(CGState* s, const double* partials, int nparts) {
     CGState& c = s[r];
     c.pAp = v;
     c.alpha = (v > 0.0) ? c.rr / v : 0.0;
+    c.rr_prev = c.rr;
   }
 }
 
-__global__ void k_cg_beta(CGState* s, const double* partials, int nparts) {
-  __shared__ double sh[4];
-  const int r = blockIdx.x;
-  if (s[r].done) return;
-  const double v = psum(partials + (size_t)r * nparts, nparts, sh);
-  if (threadIdx.x != 0) return;
-  CGState& c = s[r];
+// beta and the iteration control from the new |r|^2 = v; the denominator is
+// rr_prev, the |r|^2 the alpha step of this iteration divided by (alpha sets
+// it), so the fused beta/p kernel below can replace rr while its other
+// workgroups still divide by the old value
+__device__ inline void beta_step(CGState& c, double v) {
   c.iters += 1;
   if (!finite(v) || !finite(c.alpha)) {
     c.done = 1;
@@ -119,14 +118,21 @@ __global__ void k_cg_beta(CGState* s, const double* partials, int nparts) {
     c.skip_ru = 0;
     if (hit) c.inner_hit = 1;
   }
-  c.beta = (c.rr > 0.0) ? v / c.rr : 0.0;
-  c.rr_prev = c.rr;
+  c.beta = (c.rr_prev > 0.0) ? v / c.rr_prev : 0.0;
   c.rr = v;
   if (v > c.rr_max) c.rr_max = v;
   if (c.iters >= c.maxiter && c.skip_ru) {
     c.done = 1;
     c.status = CG_MAXITER;
   }
+}
+
+__global__ void k_cg_beta(CGState* s, const double* partials, int nparts) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x;
+  if (s[r].done) return;
+  const double v = psum(partials + (size_t)r * nparts, nparts, sh);
+  if (threadIdx.x == 0) beta_step(s[r], v);
 }
 
 // x += alpha p ; r -= alpha Ap ; |r|^2 partials   (x may be wider than r)
@@ -166,6 +172,36 @@ __global__ void k_cg_p(S* p, const S* __restrict__ r, long n, long rs, const CGS
   if (cs[q].done) return;
   using A = typename StoreTraits<S>::acc;
   const A beta = (A)cs[q].beta;
+  const size_t o = (size_t)q * rs;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    auto pv = ld(p + o + i);
+    auto rv = ld(r + o + i);
+    pv.re = rv.re + beta * pv.re;
+    pv.im = rv.im + beta * pv.im;
+    st(p + o + i, pv);
+    if (plo) st(plo + o + i, pv);
+  }
+}
+
+// beta step fused with p = r + beta p (iterations without a reliable update):
+// every workgroup sums the |r|^2 partials in the same fixed order, so all
+// agree on beta bit for bit; workgroup 0 alone updates the control state.
+// A rhs that workgroup 0 marks done meanwhile may see p updated by only some
+// workgroups, which is harmless: done is final here (only the reliable
+// update's finish kernel sets the resumable CG_STALLED).
+template <typename S, typename SL>
+__global__ void k_cg_beta_p(S* p, const S* __restrict__ r, long n, long rs, CGState* cs, SL* plo,
+                            const double* partials, int nparts) {
+  __shared__ double sh[4];
+  const int q = blockIdx.y;
+  CGState& c = cs[q];
+  if (c.done) return;
+  const double v = psum(partials + (size_t)q * nparts, nparts, sh);
+  const double rr0 = c.rr_prev;
+  if (blockIdx.x == 0 && threadIdx.x == 0) beta_step(c, v);
+  if (!finite(v)) return;
+  using A = typename StoreTraits<S>::acc;
+  const A beta = (A)((rr0 > 0.0) ? v / rr0 : 0.0);
   const size_t o = (size_t)q * rs;
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
     auto pv = ld(p + o + i);
@@ -340,6 +376,23 @@ hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nr
     k_cg_p<float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo);
   else if (prec == P_F32 && lo_prec == P_BF16)
     k_cg_p<float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, int nrhs, CGState* s,
+                            void* plo, int lo_prec, const double* partials, int nparts, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  if (prec == P_F64)
+    k_cg_beta_p<double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
+                                                       (double2*)nullptr, partials, nparts);
+  else if (prec == P_F32 && (plo == nullptr || lo_prec == P_F32))
+    k_cg_beta_p<float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo,
+                                                     partials, nparts);
+  else if (prec == P_F32 && lo_prec == P_BF16)
+    k_cg_beta_p<float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo,
+                                                     partials, nparts);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

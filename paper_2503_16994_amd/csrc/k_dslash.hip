@@ -323,6 +323,7 @@ __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
       for (int w = 0; w < kHopBlock / 64; ++w) v += sh[w];  // waves in order
       c.pAp = v;
       c.alpha = (v > 0.0) ? c.rr / v : 0.0;
+      c.rr_prev = c.rr;
     }
   }
   __syncthreads();

@@ -122,7 +122,7 @@ enum CGStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_NONFINITE =
 // CG control of one right-hand side (device memory)
 struct CGState {
   double rr;       // |r|^2 of the recursion
-  double rr_prev;
+  double rr_prev;  // |r|^2 this iteration's alpha divided by (set by alpha, read by beta)
   double rr_max;   // max |r|^2 since the last reliable update
   double pAp;      // |Dhat p|^2
   double alpha, beta;
@@ -177,6 +177,9 @@ hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, co
                         hipStream_t st);
 hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs,
                        const CGState* s, void* p_lo, int lo_prec, hipStream_t st);
+// beta step and p update in one launch (nparts |r|^2 partials per rhs)
+hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, int nrhs, CGState* s,
+                            void* p_lo, int lo_prec, const double* partials, int nparts, hipStream_t st);
 // reliable-update kernels (each skips rhs without a pending update)
 hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);

@@ -385,17 +385,19 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
 
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
   // eo: hop, hop (+g5, |Dhat p|^2), hop (+alpha), hop fused with the x/r
-  // update (+|r|^2), beta, [reliable-update group], p update
+  // update (+|r|^2), then beta fused with the p update, or, every kRuStride-th
+  // iteration, beta, the reliable-update group and the p update
   constexpr int kRuStride = 5;
   auto iteration = [&](int i) -> hipError_t {
     hipError_t e;
+    int nb_r;  // |r|^2 partials per rhs
     if (eo) {
       const int nb_it = iter_parts(c, lprec);
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
       if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
       if ((e = hop_oe_xr(c, lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
-      if ((e = launch_cg_beta(cg, parts, nb_it, N, st))) return e;
+      nb_r = nb_it;
     } else {
       if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
       if ((e = launch_cg_alpha(cg, parts, nb_op, N, st))) return e;
@@ -403,13 +405,15 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       if ((e = launch_cg_xr(xi.p, xi.prec, xi.rs, ri.p, pi.p, api.p, ri.prec, n_vec, ri.rs, N, cg, parts,
                             st)))
         return e;
-      if ((e = launch_cg_beta(cg, parts, nb_blas, N, st))) return e;
+      nb_r = nb_blas;
     }
-    if ((i + 1) % kRuStride == 0 && (e = reliable_update())) return e;
-    if ((e = launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, lo16 ? pin.p : nullptr,
-                         lo16 ? P_BF16 : P_F32, st)))
-      return e;
-    return hipSuccess;
+    void* plo = lo16 ? pin.p : nullptr;
+    const int plo_prec = lo16 ? P_BF16 : P_F32;
+    if ((i + 1) % kRuStride != 0)
+      return launch_cg_beta_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st);
+    if ((e = launch_cg_beta(cg, parts, nb_r, N, st))) return e;
+    if ((e = reliable_update())) return e;
+    return launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st);
   };
   constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
   const bool use_graph = prm->use_graph && st != nullptr;
