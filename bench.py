@@ -49,16 +49,33 @@ L_C2 = (16, 16, 16, 32)
 KAPPA, CSW, EPS, SEED, TOL = 0.1345, 1.9, 0.2, 2, 1e-10
 THETA = (1, 1, 1, -1)
 # algorithmic traffic per lattice site V (reals): each input read once, each
-# output written once (links 72, clover blocks 36, spinors 12 per parity)
-REALS_HOP_OE = 144   # U 72 + psi_o 12 + psi_e 12 + A_ee 36 + out 12
-REALS_HOP_EO = 132   # U 72 + psi_e 12 + A_oo^-1 36 + out 12
+# output written once.  Links: 4 per site of 12 reals stored as two rows
+# (paper Sec. 2.2; 18 reals with full links); clover blocks 36, spinors 12 per
+# parity.
+LINK_REALS = {True: 48, False: 72}  # per site V, two-row / full links
+
+
+def hop_reals(op, nrhs=1, two_row=True):
+    """Algorithmic reals per site V of one hop launch (or of the full Dw)."""
+    u = LINK_REALS[two_row]
+    if op == "hop_oe":   # U + psi_o + psi_e + A_ee + out
+        return u + 36 + 36 * nrhs
+    if op == "hop_eo":   # U + psi_e + A_oo^-1 + out
+        return u + 36 + 24 * nrhs
+    return u + 72 + 48 * nrhs  # full Dw: U + A + psi + out
+
+
 BYTES_PER_REAL = {0: 8, 1: 4, 2: 2}
-DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1,1>"
-# hop tuning of the benchmark step and of its roofline measurement: what the
-# autotuner picks at 16^3x32 (nr_tile, block_order, rhs_lanes, nt_store,
-# cached_gauge, occ_cap); cached gauge loads keep links and clover in the
-# last-level cache, which holds this lattice's whole working set
-STEP_TUNING = (1, 1, 1, True, True, 0)
+# the dominant kernel: the FP64 o->e hop with the clover block, direction split
+DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1,1,SPLIT>"
+# hop tuning of the benchmark step and of its roofline measurement
+# (nr_tile, block_order, rhs_lanes, nt_store, cached_gauge, occ_cap,
+# dir_split): cached gauge loads keep links and clover in the last-level
+# cache, which holds this lattice's whole working set; the direction split
+# gives the 65536 sites of a parity two waves each
+STEP_TUNING = (1, 1, 1, True, True, 0, True)
+# gauge fields of every leg store two rows per link
+TWO_ROW = True
 ROOFLINE_LAUNCHES = 100
 KERNEL_SOURCES = ["paper_2503_16994_amd/csrc/k_dslash.hip", "paper_2503_16994_amd/csrc/lqcd_dev.h"]
 
@@ -117,9 +134,11 @@ def hop_rates(g, lat_, ws, d, prec, nrhs, stream, reps=30):
     else:
         x = torch.randn(vb // 4, device="cuda").view(torch.uint8)
     y = torch.empty(vb, dtype=torch.uint8, device="cuda")
-    ops = [(lqcd.OP_HOP_EO, "hop_eo", 108 + 24 * nrhs), (lqcd.OP_HOP_OE, "hop_oe", 108 + 36 * nrhs)]
+    tr = bool(g.pmask & lqcd.PM_TWO_ROW)
+    ops = [(lqcd.OP_HOP_EO, "hop_eo", hop_reals("hop_eo", nrhs, tr)),
+           (lqcd.OP_HOP_OE, "hop_oe", hop_reals("hop_oe", nrhs, tr))]
     if prec == lqcd.F64 and nrhs == 1:
-        ops.append((lqcd.OP_DW, "dw_full", 192))  # psi 24 + U 72 + A 72 + out 24
+        ops.append((lqcd.OP_DW, "dw_full", hop_reals("dw_full", 1, tr)))
     out = {}
     for op, name, reals in ops:
         ms = time_launches(lambda op=op: lqcd.dw_apply_internal(g, d, x, y, op, prec, nrhs, ws, stream=stream),
@@ -178,11 +197,12 @@ def main():
         profile_kernels(stream)
         return
     pm = lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16
+    gpm = pm | (lqcd.PM_TWO_ROW if TWO_ROW else 0)  # gauge fields
 
     # ---- the step: 16^3x32, 12 sources, FP64 eo-CG one at a time -------------
     U2 = inputs.gauge_field(L_C2, EPS, seed=SEED)
     lat = lqcd.Lattice(L_C2, lqcd.BC_PERIODIC, THETA)
-    gauge = lqcd.GaugeField(lat, torch.from_numpy(U2), pm, stream=stream)
+    gauge = lqcd.GaugeField(lat, torch.from_numpy(U2), gpm, stream=stream)
     eta = torch.from_numpy(inputs.point_sources_12(L_C2, (0, 0, 0, 0))).cuda()
     psi = torch.empty_like(eta)
     ws1 = lqcd.Workspace(lat, pm, 1)
@@ -239,13 +259,14 @@ def main():
     e1.synchronize()
     ms_oe = e0.elapsed_time(e1) / ROOFLINE_LAUNCHES
     del graph
-    alg_bytes = REALS_HOP_OE * BYTES_PER_REAL[0] * lat.volume
+    alg_bytes = hop_reals("hop_oe", 1, TWO_ROW) * BYTES_PER_REAL[0] * lat.volume
     achieved = alg_bytes / (ms_oe * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(DOMINANT_KERNEL, tune_roof),
                 "kernel": DOMINANT_KERNEL, "avg_launch_us": round(ms_oe * 1e3, 2),
                 "alg_bytes_per_launch": alg_bytes, "tuning": tune_roof,
-                "note": "16^3x32 working set (~150 MB) fits the 256 MB last-level cache; "
+                "links": "two rows per link" if TWO_ROW else "full",
+                "note": "16^3x32 working set (~130 MB) fits the 256 MB last-level cache; "
                         "HBM-resident figures in dw_hbm"}
     log(f"roofline: {roofline}")
     del vin, vout
@@ -286,13 +307,13 @@ def main():
         mixed = mixed_leg(gauge, lat, ws12, eta, KAPPA, CSW, value, args.steps, args.warmup, "16^3x32")
         del ws12
         torch.cuda.empty_cache()
-        mixed_c4 = c4_leg(stream, pm, mixed_leg, 1)
+        mixed_c4 = c4_leg(stream, pm, gpm, mixed_leg, 1)
 
     # ---- 32^3x64: Z2 solve, 12-source propagator and the kernels' HBM rates --
     ctx = None
     if not args.no_hbm:
-        c3, dw_hbm = c3_leg(stream, pm, args.no_mixed, mixed_leg)
-        ctx = ctx_leg(stream)
+        c3, dw_hbm = c3_leg(stream, pm, gpm, args.no_mixed, mixed_leg)
+        ctx = ctx_leg(stream, gpm & (lqcd.PM_F64 | lqcd.PM_TWO_ROW))
 
     # ---- serving -------------------------------------------------------------
     if not args.no_serve:
@@ -315,7 +336,9 @@ def main():
         "config": {"workload": "16^3x32 Wilson-clover propagator: 12 point sources solved one at a "
                                "time, FP64 even-odd CG, tol 1e-10",
                    "lattice": list(L_C2), "kappa": KAPPA, "csw": CSW, "bc": "periodic/antiperiodic",
-                   "link_eps": EPS, "sources": 12, "tol": TOL, "solver": "eo-CG FP64, hipGraph chunks"},
+                   "link_eps": EPS, "sources": 12, "tol": TOL, "solver": "eo-CG FP64, hipGraph chunks",
+                   "links": "two rows per link (third rebuilt in registers)" if TWO_ROW else "full",
+                   "hop_tuning": tune64},
         "iters_per_solve": iters, "max_true_residual": rho_max,
         "roofline": roofline, "mixed": mixed, "mixed_c4": mixed_c4, "c3": c3, "dw_hbm": dw_hbm, "ctx": ctx,
         "serving": serving, "cpu_baseline": cpu,
@@ -323,7 +346,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def c4_leg(stream, pm, mixed_leg, steps):
+def c4_leg(stream, pm, gpm, mixed_leg, steps):
     """24^3x48 SF propagator: FP64 one source at a time vs mixed multi-RHS."""
     import torch
 
@@ -332,10 +355,11 @@ def c4_leg(stream, pm, mixed_leg, steps):
     kappa, csw = 0.134, 1.8
     U4 = inputs.gauge_field(L4, EPS, seed=4, bc=lqcd.BC_SF)
     lat4 = lqcd.Lattice(L4, lqcd.BC_SF, (1, 1, 1, 1))
-    g4 = lqcd.GaugeField(lat4, torch.from_numpy(U4), pm, stream=stream)
+    g4 = lqcd.GaugeField(lat4, torch.from_numpy(U4), gpm, stream=stream)
     del U4
     eta4 = torch.from_numpy(inputs.point_sources_12(L4, (0, 0, 0, 1))).cuda()
     ws1 = lqcd.Workspace(lat4, pm, 1)
+    lqcd.set_tuning(ws1, lqcd.F64, dir_split=True)
     lqcd.autotune(g4, lqcd.dirac(kappa, csw), lqcd.F64, 1, ws1, stream=stream)
 
     def fstep():
@@ -357,7 +381,7 @@ def c4_leg(stream, pm, mixed_leg, steps):
     return out
 
 
-def c3_leg(stream, pm, no_mixed, mixed_leg):
+def c3_leg(stream, pm, gpm, no_mixed, mixed_leg):
     """32^3x64: Z2-noise solve in FP64/FP32/BF16, the 12-source propagator
     (FP64 one source at a time vs 12 rhs in one solve) and the hop kernels'
     HBM rates."""
@@ -368,12 +392,13 @@ def c3_leg(stream, pm, no_mixed, mixed_leg):
     kappa = 0.135
     U3 = inputs.gauge_field(L3, EPS, seed=3)
     lat3 = lqcd.Lattice(L3, lqcd.BC_PERIODIC, THETA)
-    g3 = lqcd.GaugeField(lat3, torch.from_numpy(U3), pm, stream=stream)
+    g3 = lqcd.GaugeField(lat3, torch.from_numpy(U3), gpm, stream=stream)
     del U3
     ws3 = lqcd.Workspace(lat3, pm, 1)
     d3 = lqcd.dirac(kappa, CSW)
     dw_hbm = {"lattice": list(L3)}
     for prec, pname in ((lqcd.F64, "f64"), (lqcd.F32, "f32"), (lqcd.BF16, "bf16")):
+        lqcd.set_tuning(ws3, prec, dir_split=True)
         tune, _ = lqcd.autotune(g3, d3, prec, 1, ws3, stream=stream)
         for k, v in hop_rates(g3, lat3, ws3, d3, prec, 1, stream).items():
             dw_hbm[f"{k}_{pname}"] = dict(v, tuning=tune)
@@ -419,7 +444,7 @@ def c3_leg(stream, pm, no_mixed, mixed_leg):
     return c3, dw_hbm
 
 
-def ctx_leg(stream):
+def ctx_leg(stream, gpm):
     """The shape of the paper's CG timing: 1000 FP64 full-lattice CG
     iterations on a 32^4 lattice (periodic space, antiperiodic time, one
     point source).  Context only: the paper's fields, parameters and
@@ -430,10 +455,11 @@ def ctx_leg(stream):
     L = (32, 32, 32, 32)
     U = inputs.gauge_field(L, EPS, seed=5)
     lat = lqcd.Lattice(L, lqcd.BC_PERIODIC, THETA)
-    g = lqcd.GaugeField(lat, torch.from_numpy(U), lqcd.PM_F64, stream=stream)
+    g = lqcd.GaugeField(lat, torch.from_numpy(U), gpm, stream=stream)
     del U
     ws = lqcd.Workspace(lat, lqcd.PM_F64, 1)
     eta = torch.from_numpy(inputs.point_source(L)[None]).cuda()
+    lqcd.set_tuning(ws, lqcd.F64, dir_split=True)
     lqcd.autotune(g, lqcd.dirac(KAPPA, CSW), lqcd.F64, 1, ws, stream=stream)
 
     def run():
@@ -467,8 +493,9 @@ def serve_leg(n_requests, rate, U16, seed=99):
     etas = {}
     for i, L in enumerate(lats):
         U = U16 if L == L_C2 else inputs.gauge_field(L, EPS, seed=50 + i)
-        gids[(L, lqcd.BC_PERIODIC)] = srv.add_gauge(L, lqcd.BC_PERIODIC, THETA, U, pm)
-        gids[(L, lqcd.BC_OPEN)] = srv.add_gauge(L, lqcd.BC_OPEN, (1, 1, 1, 1), U, pm)
+        gpm = pm | (lqcd.PM_TWO_ROW if TWO_ROW else 0)
+        gids[(L, lqcd.BC_PERIODIC)] = srv.add_gauge(L, lqcd.BC_PERIODIC, THETA, U, gpm)
+        gids[(L, lqcd.BC_OPEN)] = srv.add_gauge(L, lqcd.BC_OPEN, (1, 1, 1, 1), U, gpm)
         del U
         src = inputs.point_sources_12(L, (0, 0, 0, 0))
         etas[(L, 12)] = (src, np.empty_like(src))
@@ -525,10 +552,11 @@ def serve_leg(n_requests, rate, U16, seed=99):
 def profile_kernels(stream):
     """Launch sequence for rocprofv3 runs: a plain 1 GiB device copy (to
     calibrate FETCH_SIZE/WRITE_SIZE against known bytes, and the copy rate), a
-    1 GiB read-only sum (read rate), then 20 launches of each hop kernel:
-    FP64 at 16^3x32 and at 32^3x64, FP32 and BF16 at 32^3x64 (one rhs), and
-    FP32 with 12 rhs at 32^3x64 (rhs tile 3); at 16^3x32 in the benchmark
-    step's tuning, at 32^3x64 with block order 2 and non-temporal stores."""
+    1 GiB read-only sum (read rate), then 20 launches of each hop kernel, all
+    on two-row links: FP64 at 16^3x32 and at 32^3x64, FP32 and BF16 at
+    32^3x64 (one rhs), and FP32 with 12 rhs at 32^3x64 (rhs tile 3); at
+    16^3x32 in the benchmark step's tuning, at 32^3x64 with block order 2,
+    non-temporal stores and (one rhs) the direction split."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -547,15 +575,17 @@ def profile_kernels(stream):
         big = L[3] == 64
         U = inputs.gauge_field(L, EPS, seed=SEED)
         lat = lqcd.Lattice(L, lqcd.BC_PERIODIC, THETA)
-        g = lqcd.GaugeField(lat, torch.from_numpy(U), pm if big else lqcd.PM_F64, stream=stream)
+        g = lqcd.GaugeField(lat, torch.from_numpy(U), (pm if big else lqcd.PM_F64) | lqcd.PM_TWO_ROW,
+                            stream=stream)
         del U
         nr = 12 if big else 1
         ws = lqcd.Workspace(lat, pm if big else lqcd.PM_F64, nr)
         d = lqcd.dirac(KAPPA, CSW)
-        # (nr_tile, block_order, rhs_lanes, nt_store): what the autotuner picks
-        cases = [(lqcd.F64, 1, STEP_TUNING if not big else (1, 2, 1, True))]
+        # (nr_tile, block_order, rhs_lanes, nt_store, cached_gauge, occ_cap, dir_split)
+        one = (1, 2, 1, True, False, 0, True)
+        cases = [(lqcd.F64, 1, STEP_TUNING if not big else one)]
         if big:
-            cases += [(lqcd.F32, 1, (1, 2, 1, True)), (lqcd.BF16, 1, (1, 2, 1, True)), (lqcd.F32, 12, (3, 2, 1, True))]
+            cases += [(lqcd.F32, 1, one), (lqcd.BF16, 1, one), (lqcd.F32, 12, (3, 2, 1, True))]
         for prec, nrhs, tune in cases:
             lqcd.set_tuning(ws, prec, *tune)
             vb = lqcd.vec_bytes(lat, prec, nrhs, 2)

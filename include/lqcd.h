@@ -95,8 +95,13 @@ int64_t lqcd_geom_volume(const lqcd_geom_t *g);
 
 /* ---- precisions --------------------------------------------------------- */
 enum { LQCD_F64 = 0, LQCD_F32 = 1, LQCD_BF16 = 2 };
-/* Bit masks naming the precisions a gauge field or workspace must hold. */
-enum { LQCD_PM_F64 = 1, LQCD_PM_F32 = 2, LQCD_PM_BF16 = 4 };
+/* Bit masks naming the precisions a gauge field or workspace must hold.
+ * LQCD_PM_TWO_ROW (gauge fields only) stores every link, in every precision,
+ * as its first two rows: the paper's SU(3) type (Sec. 2.2) keeps two rows
+ * and recovers the third from unitarity and unit determinant, row 2 =
+ * complex conjugate of (row 0 x row 1).  This moves 12 instead of 18 reals
+ * per link and is exact (to rounding) for SU(3) links only. */
+enum { LQCD_PM_F64 = 1, LQCD_PM_F32 = 2, LQCD_PM_BF16 = 4, LQCD_PM_TWO_ROW = 8 };
 
 /* ---- gauge field (paper Sec. 2.2: device-resident vector_field) -------- */
 typedef struct lqcd_gauge lqcd_gauge_t;
@@ -109,8 +114,12 @@ size_t lqcd_gauge_bytes(const lqcd_geom_t *g, int pmask);
  * the call's device work) into `mem` (device, >= lqcd_gauge_bytes) in the
  * internal layout, in FP64 and in the other precisions of pmask (FP32 and
  * BF16 by round-to-nearest-even).  U is used as given, except that with
- * LQCD_BC_OPEN the stored U_t(t = T-1) is set to zero.  The handle refers to
- * g and mem: both must outlive it. */
+ * LQCD_BC_OPEN the stored U_t(t = T-1) is set to zero.  With LQCD_PM_TWO_ROW
+ * the call also checks, on the device, that every link's third row equals
+ * the one rebuilt from its first two within 1e-10 (absolute, per complex
+ * element); it then waits for the stream and returns LQCD_EINVAL, with no
+ * handle, for a field that is not SU(3).  The handle refers to g and mem:
+ * both must outlive it. */
 int lqcd_gauge_create(const lqcd_geom_t *g, const void *U_dev, int pmask, void *mem,
                       size_t mem_bytes, void *stream, lqcd_gauge_t **out);
 void lqcd_gauge_free(lqcd_gauge_t *u);
@@ -194,15 +203,25 @@ typedef struct lqcd_tuning {
                           are read with ordinary (cached) loads instead of
                           non-temporal ones; bits 2-3 (level << 
                           LQCD_TUNE_OCC_SHIFT): at most 4, 3 or 2 resident
-                          workgroups per CU for level 1, 2, 3 (0: no cap) */
+                          workgroups per CU for level 1, 2, 3 (0: no cap);
+                          LQCD_TUNE_DIR_SPLIT: launches with one rhs per
+                          thread (nr_tile 1, rhs_lanes 1) give each site two
+                          waves, one for the x and y hops and one for the z
+                          and t hops, each then producing one chirality of the
+                          output: twice the parallelism for lattices too small
+                          to fill the GPU */
 } lqcd_tuning;
-enum { LQCD_TUNE_NT_STORE = 1, LQCD_TUNE_CACHED_GAUGE = 2, LQCD_TUNE_OCC_SHIFT = 2 };
+enum { LQCD_TUNE_NT_STORE = 1, LQCD_TUNE_CACHED_GAUGE = 2, LQCD_TUNE_OCC_SHIFT = 2,
+       LQCD_TUNE_DIR_SPLIT = 16 };
 
 /* Hop-kernel configuration used by a workspace for precision `prec`
  * (default: nr_tile 1, block_order 1, rhs_lanes 1).  A launch over n rhs uses
  * the largest rhs_lanes and nr_tile not above these whose product divides n.
  * EINVAL for values out of range.  None of these changes the arithmetic of
- * any rhs. */
+ * any rhs, except LQCD_TUNE_DIR_SPLIT: with it the eight hop terms of a site
+ * are summed as (x, y terms) + (z, t terms) rather than in one chain, which
+ * changes results in the last bits (results are bitwise reproducible for a
+ * given split setting). */
 int lqcd_ws_set_tuning(lqcd_ws_t *w, int prec, const lqcd_tuning *t);
 int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
 
@@ -210,7 +229,10 @@ int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
  * dividing nrhs, block_order, flags) of one Schur-operator application (both hop kernels)
  * in precision `prec` on nrhs fields of the workspace, with HIP events on
  * `stream`, at the workspace's real lattice shape; stores the fastest in the
- * workspace and returns it with its time in microseconds.  Overwrites the
+ * workspace and returns it with its time in microseconds.  The
+ * LQCD_TUNE_DIR_SPLIT bit is the caller's choice and is kept as set in the
+ * workspace; with it set only nr_tile = rhs_lanes = 1 (the shape it applies
+ * to) is searched, so autotuning never changes a result.  Overwrites the
  * workspace's vectors (not its clover term).  Requires nrhs <= the
  * workspace's nrhs and `prec` held by gauge field and workspace. */
 int lqcd_autotune(const lqcd_gauge_t *u, const lqcd_dirac *d, int prec, int nrhs, lqcd_ws_t *w,

@@ -19,7 +19,7 @@ Sheikholeslami-Wohlert operator the paper cites):
 
 Functions with a pin in ``tests/test_oracle_pins.py``: ``gamma``,
 ``field_strength``, ``clover_matrix``, ``hop``, ``dw``, ``dw_dag``, ``cg``,
-``schur_*``.  None is "parity unpinned".
+``schur_*``, ``su3_from_two_rows``.  None is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -251,6 +251,20 @@ def schur_reconstruct(L, bc, theta, U, Ainv, eta, psi_e) -> np.ndarray:
     if bc == SF:
         out[0] = 0.0
     return out
+
+
+def su3_from_two_rows(U2) -> np.ndarray:
+    """Links ``U[..., 3, 3]`` from their first two rows ``U2[..., 2, 3]``.
+
+    Paper Sec. 2.2: the SU(3) element type stores two rows; the third follows
+    from U^-1 = U^+ and det U = 1.  Together these make U^+ the adjugate of U,
+    so every entry of row 2 is the complex conjugate of its cofactor, which is
+    built from rows 0 and 1 alone: row 2 = conj(row 0 x row 1).  (For a
+    unitary U of determinant d the same formula gives conj(d) times row 2.)"""
+    U2 = np.asarray(U2, np.complex128)
+    r0, r1 = U2[..., 0, :], U2[..., 1, :]
+    r2 = np.conj(np.cross(r0, r1))
+    return np.stack([r0, r1, r2], axis=-2)
 
 
 def dense_dw(L, bc, theta, U, A) -> np.ndarray:

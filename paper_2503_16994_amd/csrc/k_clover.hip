@@ -70,8 +70,8 @@ __device__ inline M3 m3_mul_dn(const M3& a, const M3& b) {
   return r;
 }
 
-__device__ inline M3 load_link(const KGeom& g, const double2* U, int x, int y, int z, int t,
-                               int mu) {
+__device__ inline M3 load_link(const KGeom& g, const double2* U, bool two_row, int x, int y, int z,
+                               int t, int mu) {
   x = (x + g.L[0]) % g.L[0];
   y = (y + g.L[1]) % g.L[1];
   z = (z + g.L[2]) % g.L[2];
@@ -79,23 +79,33 @@ __device__ inline M3 load_link(const KGeom& g, const double2* U, int x, int y, i
   const long lex = x + (long)g.L[0] * (y + (long)g.L[1] * (z + (long)g.L[2] * t));
   const int p = (x + y + z + t) & 1;
   const size_t s = (size_t)(lex >> 1);
-  const double2* u = U + (size_t)p * 36 * g.V2p + tix(s, 36) + mu * 9 * kTile;
+  const int ne = two_row ? 6 : 9;  // stored complex per link
+  const double2* u = U + (size_t)p * 4 * ne * g.V2p + tix(s, 4 * ne) + mu * ne * kTile;
   M3 r;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
+  for (int e = 0; e < 6; ++e) {
     double2 v = u[e * kTile];
     r.m[e] = {v.x, v.y};
+  }
+  if (two_row) {
+    su3_third_row(r.m);
+  } else {
+#pragma unroll
+    for (int e = 6; e < 9; ++e) {
+      double2 v = u[e * kTile];
+      r.m[e] = {v.x, v.y};
+    }
   }
   return r;
 }
 
 // traceless anti-Hermitian part of (Q - Q^+)/8 for the (mu, nu) plane at x
-__device__ inline M3 field_strength(const KGeom& g, const double2* U, const int (&x)[4], int mu,
-                                    int nu) {
+__device__ inline M3 field_strength(const KGeom& g, const double2* U, bool two_row, const int (&x)[4],
+                                    int mu, int nu) {
   int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0};
   dm[mu] = 1;
   dn[nu] = 1;
-#define LNK(ox, oy, oz, ot, d) load_link(g, U, x[0] + (ox), x[1] + (oy), x[2] + (oz), x[3] + (ot), d)
+#define LNK(ox, oy, oz, ot, d) load_link(g, U, two_row, x[0] + (ox), x[1] + (oy), x[2] + (oz), x[3] + (ot), d)
   const M3 Um_x = LNK(0, 0, 0, 0, mu);
   const M3 Un_x = LNK(0, 0, 0, 0, nu);
   const M3 Un_xpm = LNK(dm[0], dm[1], dm[2], dm[3], nu);
@@ -231,12 +241,12 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
   const size_t par = (size_t)p * 36 * g.V2p;  // parity p of the clover field
 
   // planes: 0 xy, 1 xz, 2 xt, 3 yz, 4 yt, 5 zt
-  const M3 Fxy = field_strength(g, c.U64, x, 0, 1);
-  const M3 Fxz = field_strength(g, c.U64, x, 0, 2);
-  const M3 Fxt = field_strength(g, c.U64, x, 0, 3);
-  const M3 Fyz = field_strength(g, c.U64, x, 1, 2);
-  const M3 Fyt = field_strength(g, c.U64, x, 1, 3);
-  const M3 Fzt = field_strength(g, c.U64, x, 2, 3);
+  const M3 Fxy = field_strength(g, c.U64, c.two_row != 0, x, 0, 1);
+  const M3 Fxz = field_strength(g, c.U64, c.two_row != 0, x, 0, 2);
+  const M3 Fxt = field_strength(g, c.U64, c.two_row != 0, x, 0, 3);
+  const M3 Fyz = field_strength(g, c.U64, c.two_row != 0, x, 1, 2);
+  const M3 Fyt = field_strength(g, c.U64, c.two_row != 0, x, 1, 3);
+  const M3 Fzt = field_strength(g, c.U64, c.two_row != 0, x, 2, 3);
 
   const int T = g.L[3];
   bool bnd = false;

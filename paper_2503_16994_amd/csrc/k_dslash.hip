@@ -5,8 +5,9 @@
 // rhs groups (so a 128-thread workgroup covers 128/RL sites and RL*NR rhs;
 // 128 rather than 256 threads gives the one-rhs launches on a 16^3x32 lattice
 // two workgroups per CU instead of one).  Per
-// hop a thread loads the link (9 site-coalesced complex loads; the RL lanes of
-// a site issue identical addresses, which the memory pipeline serves once)
+// hop a thread loads the link (9 site-coalesced complex loads, or 6 when the
+// field keeps two rows per link and the third is rebuilt in registers; the RL
+// lanes of a site issue identical addresses, which the memory pipeline serves once)
 // and, for each of its NR rhs, the neighbour spinor (12 loads), spin-projects
 // it to a half spinor, multiplies by U or U^+ and accumulates.  The clover
 // blocks (two Hermitian 6x6 blocks) are loaded one chirality at a time and
@@ -45,15 +46,25 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
   if (pr == (A)0 && pi == (A)0) return;
 
   const int sn = nb_index(g, s, c, MU, DIR);
-  const size_t par = (size_t)36 * g.V2p;  // one parity of the link field
+  const int ne = a.two_row ? 6 : 9;                // stored complex per link
+  const size_t par = (size_t)4 * ne * g.V2p;      // one parity of the link field
   const SG* Ub = static_cast<const SG*>(a.U);
-  const SG* up = (DIR > 0) ? Ub + p * par + tix(s, 36) + MU * 9 * kTile
-                           : Ub + (1 - p) * par + tix(sn, 36) + MU * 9 * kTile;
+  const SG* up = (DIR > 0) ? Ub + p * par + tix(s, 4 * ne) + MU * ne * kTile
+                           : Ub + (1 - p) * par + tix(sn, 4 * ne) + MU * ne * kTile;
   cpx<A> U[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
+  for (int e = 0; e < 6; ++e) {
     auto v = a.cached_gauge ? ld(up + e * kTile) : ld_nt(up + e * kTile);
     U[e] = {(A)v.re, (A)v.im};
+  }
+  if (a.two_row) {
+    su3_third_row(U);
+  } else {
+#pragma unroll
+    for (int e = 6; e < 9; ++e) {
+      auto v = a.cached_gauge ? ld(up + e * kTile) : ld_nt(up + e * kTile);
+      U[e] = {(A)v.re, (A)v.im};
+    }
   }
 
 #pragma unroll
@@ -177,12 +188,25 @@ __device__ inline double block_sum_rl(double v, double* sh) {
 // coordinates and the rhs indices in the outputs.
 struct ThreadSite {
   int sb, rhs_tile0, rhs0, s, p;
+  int c0;  // first output component this thread owns (0, or 6 w when split)
   bool active, masked;
 };
 
-template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL, typename A>
-__device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v)[NR][12]) {
-  constexpr int SPB = kHopBlock / RL;  // sites per block
+// Direction split (SPLIT; one rhs per thread only).  The two waves of a
+// workgroup share its 64 sites: wave w computes the hops in directions 2w and
+// 2w+1, the waves swap halves of their partial sums through LDS (xch, 2 x 6 x 64
+// complex), and wave w then owns the six output components of chirality w
+// (spins 2w, 2w+1) and their clover block.  Twice the waves per site at half
+// the dependent loads each: for lattices too small to fill the GPU.  The hop
+// sum is (x, y terms) + (z, t terms) instead of one chain over the eight, so
+// results differ from the unsplit kernel in the last bits.
+template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT, typename A>
+__device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v)[NR][12], cpx<A>* xch) {
+  static_assert(!SPLIT || (NR == 1 && RL == 1 && HOP), "direction split: one rhs per thread");
+  constexpr int SPB = SPLIT ? 64 : kHopBlock / RL;  // sites per block
+  // wave index (uniform over the wave; only the split uses it)
+  const int wv = SPLIT ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+  ts.c0 = 6 * wv;
   const KGeom& g = a.g;
   int tile, p = a.p_out, b = blockIdx.x, nb = gridDim.x, nbs = a.nbs;
   if (a.both) {  // parity 0 in the first half of the grid, parity 1 in the second
@@ -204,7 +228,7 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
     if (all) return false;
   }
   ts.p = p;
-  const int s = bx * SPB + (int)(threadIdx.x / RL);
+  const int s = bx * SPB + (SPLIT ? (int)(threadIdx.x & 63) : (int)(threadIdx.x / RL));
   ts.s = s;
   ts.active = s < g.V2;
   const SI* yb = static_cast<const SI*>(a.y);
@@ -230,18 +254,82 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
   if (ts.active) {
     c = site_coord(g, s, p);
     if (HOP) {
-      hop_dir<0, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<0, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<1, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<1, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<2, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<2, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<3, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      hop_dir<3, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      if (!SPLIT || wv == 0) {
+        hop_dir<0, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<0, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<1, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<1, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      }
+      if (!SPLIT || wv == 1) {
+        hop_dir<2, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<2, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<3, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+        hop_dir<3, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      }
     }
   }
   ts.masked = (g.bc == BC_SF) && (c.t == 0);
   const A scale = (A)a.scale;
+
+  if constexpr (SPLIT) {
+    // region 0 of xch receives wave 1's spins 0, 1 (for wave 0), region 1
+    // wave 0's spins 2, 3 (for wave 1); every thread of the workgroup gets here
+    const int l = threadIdx.x & 63;
+    if (wv == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xch[(6 + k) * 64 + l] = acc[0][2 + k / 3][k % 3];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xch[k * 64 + l] = acc[0][k / 3][k % 3];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[0][k] = cscale(scale, cadd(acc[0][k / 3][k % 3], xch[k * 64 + l]));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        v[0][k] = cscale(scale, cadd(xch[(6 + k) * 64 + l], acc[0][2 + k / 3][k % 3]));
+    }
+    if (ts.active && PRE != PRE_NONE) {
+      cpx<A> Cm[18];
+      if (PRE == PRE_CLOV) load_block(cpre, wv, s, a.cached_gauge != 0, Cm);
+      const SI* zp = zb + (size_t)rhs0 * a.z_rs + tix(s, 12) + 6 * wv * kTile;
+      cpx<A> in6[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        auto t = ld(zp + i * kTile);
+        in6[i] = {(A)t.re, (A)t.im};
+      }
+      if (PRE == PRE_IDENT) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[0][i] = cadd(v[0][i], in6[i]);
+      } else {
+        cpx<A> o6[6];
+        herm6_mul(Cm, in6, o6);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[0][i] = cadd(v[0][i], o6[i]);
+      }
+    }
+    if (ts.active && POST == POST_CLOV) {
+      cpx<A> Ci[18], in6[6], o6[6];
+      load_block(static_cast<const SG*>(a.Cpost), wv, s, a.cached_gauge != 0, Ci);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) in6[i] = v[0][i];
+      herm6_mul(Ci, in6, o6);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[0][i] = o6[i];
+    }
+    if (a.g5 && wv == 1) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[0][k] = {-v[0][k].re, -v[0][k].im};
+    }
+    if (ts.masked) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[0][k] = {(A)0, (A)0};
+    }
+    return true;
+  }
 
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -329,14 +417,16 @@ __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
   __syncthreads();
 }
 
-template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL>
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT>
 __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
+  constexpr int NC = SPLIT ? 6 : 12;  // output components per thread
   __shared__ double red[(kHopBlock / 64) * RL > 4 ? (kHopBlock / 64) * RL : 4];
+  __shared__ cpx<A> xch[SPLIT ? 2 * 6 * 64 : 1];
   if (a.alpha_cg) fused_alpha(a, red);
   ThreadSite ts;
   cpx<A> v[NR][12];
-  if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL>(a, ts, v)) return;
+  if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL, SPLIT>(a, ts, v, xch)) return;
   SO* ob = static_cast<SO*>(a.out);
   if (a.both) ob += ts.p * a.par_stride;
   // padding sites of the last tile (inactive, v = 0) are written too, so
@@ -346,17 +436,17 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   for (int r = 0; r < NR; ++r) {
     double nrm = 0.0;
     if (store) {
-      SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + tix(ts.s, 12);
+      SO* op = ob + (size_t)(ts.rhs0 + r) * a.out_rs + tix(ts.s, 12) + ts.c0 * kTile;
       if (a.nt_out) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) st_nt(op + k * kTile, v[r][k]);
+        for (int k = 0; k < NC; ++k) st_nt(op + k * kTile, v[r][k]);
       } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) st(op + k * kTile, v[r][k]);
+        for (int k = 0; k < NC; ++k) st(op + k * kTile, v[r][k]);
       }
       if (a.partials) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
+        for (int k = 0; k < NC; ++k)
           nrm += (double)v[r][k].re * (double)v[r][k].re + (double)v[r][k].im * (double)v[r][k].im;
       }
     }
@@ -372,14 +462,16 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
 // Ap = g5 (A_ee q + 1/2 H t) computed in registers, every rhs that is not done
 // gets x += alpha p, r -= alpha Ap (x, r, p of type SV at this site) and the
 // per-block |r|^2 partial.  Ap is never stored.
-template <typename SG, typename SI, typename SV, int NR, int RL>
+template <typename SG, typename SI, typename SV, int NR, int RL, bool SPLIT>
 __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
   using AV = typename StoreTraits<SV>::acc;
+  constexpr int NC = SPLIT ? 6 : 12;  // output components per thread
   __shared__ double red[(kHopBlock / 64) * RL];
+  __shared__ cpx<A> xch[SPLIT ? 2 * 6 * 64 : 1];
   ThreadSite ts;
   cpx<A> v[NR][12];
-  if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL>(a, ts, v)) return;
+  if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL, SPLIT>(a, ts, v, xch)) return;
   SV* xb = static_cast<SV*>(a.xr_x);
   SV* rb = static_cast<SV*>(a.xr_r);
   const SV* pb = static_cast<const SV*>(a.xr_p);
@@ -391,9 +483,10 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
     if (ts.active && !cs.done) {
       const double alpha_d = cs.alpha;
       const AV alpha = (AV)alpha_d;
-      const size_t o = (size_t)q * a.xr_rs + tix(ts.s, 12), ox = (size_t)q * a.xr_xrs + tix(ts.s, 12);
+      const size_t o = (size_t)q * a.xr_rs + tix(ts.s, 12) + ts.c0 * kTile,
+                   ox = (size_t)q * a.xr_xrs + tix(ts.s, 12) + ts.c0 * kTile;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
+      for (int k = 0; k < NC; ++k) {
         auto pv = ld(pb + o + k * kTile);
         auto xv = ld(xb + ox + k * kTile);
         auto rv = ld(rb + o + k * kTile);
@@ -412,7 +505,11 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   }
 }
 
-static int sites_per_block(int rl) { return kHopBlock / (rl < 1 ? 1 : rl); }
+static int sites_per_block(int rl, bool split = false) {
+  return split ? 64 : kHopBlock / (rl < 1 ? 1 : rl);
+}
+// the direction split applies to launches with one rhs per thread only
+static bool split_on(const HopLaunch& h) { return h.dir_split && h.nr_tile == 1 && h.rhs_lanes == 1; }
 
 // Unused dynamic LDS that caps the workgroups resident per CU (160 KiB of LDS
 // per CU, plus each workgroup's small static reduction array): level 1 -> 4,
@@ -428,15 +525,15 @@ static unsigned lds_cap_bytes(int level) {
 }
 
 // most partial sums per rhs any hop launch writes on V2 sites per parity:
-// 4 rhs lanes (fewest sites per workgroup), or both parities with one lane
+// 4 rhs lanes (fewest sites per workgroup), or both parities split
 int hop_max_parts(long V2) {
   const long one = (V2 + sites_per_block(4) - 1) / sites_per_block(4);
-  const long both = 2 * ((V2 + sites_per_block(1) - 1) / sites_per_block(1));
+  const long both = 2 * ((V2 + sites_per_block(1, true) - 1) / sites_per_block(1, true));
   return (int)(one > both ? one : both);
 }
 
 int hop_nblocks(const HopLaunch& h) {
-  const int spb = sites_per_block(h.rhs_lanes);
+  const int spb = sites_per_block(h.rhs_lanes, split_on(h));
   const int nb = (h.g.V2 + spb - 1) / spb;
   return h.both ? 2 * nb : nb;
 }
@@ -455,7 +552,7 @@ static bool prepare(HopLaunch& h) {
   if (h.nrhs % (h.nr_tile * h.rhs_lanes) != 0) return false;
   h.nbs = hop_nblocks(h);
   h.lds_cap = lds_cap_bytes(h.occ_cap);
-  const int spb = sites_per_block(h.rhs_lanes);
+  const int spb = sites_per_block(h.rhs_lanes, split_on(h));
   const long P = (long)h.g.Lxh * h.g.L[1];
   h.bpp = (int)(P / spb);
   const bool slab_ok = (h.g.L[2] % 8) == 0 && (P % spb) == 0;
@@ -470,9 +567,17 @@ template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, in
 static hipError_t launch_rl(const HopLaunch& h, hipStream_t st) {
   const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
   switch (h.nr_tile) {
-    case 1: k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 1:
+      if constexpr (RL == 1) {
+        if (split_on(h)) {
+          k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          break;
+        }
+      }
+      k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
+    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -500,9 +605,17 @@ template <typename SG, typename SI, typename SV, int RL>
 static hipError_t launch_xr_rl(const HopLaunch& h, hipStream_t st) {
   const unsigned grid = (unsigned)h.nbs * (unsigned)(h.nrhs / (h.nr_tile * RL));
   switch (h.nr_tile) {
-    case 1: k_hop_xr<SG, SI, SV, 1, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 2: k_hop_xr<SG, SI, SV, 2, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 3: k_hop_xr<SG, SI, SV, 3, RL><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 1:
+      if constexpr (RL == 1) {
+        if (split_on(h)) {
+          k_hop_xr<SG, SI, SV, 1, 1, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          break;
+        }
+      }
+      k_hop_xr<SG, SI, SV, 1, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
+    case 2: k_hop_xr<SG, SI, SV, 2, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 3: k_hop_xr<SG, SI, SV, 3, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -544,9 +657,10 @@ static hipError_t launch_single(const HopLaunch& h0, hipStream_t st) {
   HopLaunch h = h0;
   h.nr_tile = 1;
   h.rhs_lanes = 1;
+  h.dir_split = 0;
   if (!prepare(h)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)h.nbs * (unsigned)h.nrhs;
-  k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1><<<grid, kHopBlock, 0, st>>>(h);
+  k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, false><<<grid, kHopBlock, 0, st>>>(h);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ __device__ inline double block_sum256(double v, double* sh) {
 // Gauge import
 // ---------------------------------------------------------------------------
 __global__ void k_import_gauge(KGeom g, const double2* __restrict__ Uc, double2* U64, float2* U32,
-                               bf16x2* U16) {
+                               bf16x2* U16, bool two_row, int* bad) {
   const long V = 2L * g.V2;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;  // (site, mu)
   if (i >= 4 * V) return;
@@ -43,21 +43,37 @@ __global__ void k_import_gauge(KGeom g, const double2* __restrict__ Uc, double2*
   const int p = (x + y + z + t) & 1;
   const long s = lex >> 1;
   const bool zero = (g.bc == BC_OPEN) && (mu == 3) && (t == g.L[3] - 1);
-  const size_t base = (size_t)p * 36 * g.V2p + tix(s, 36) + mu * 9 * kTile;
+  const int ne = two_row ? 6 : 9;  // stored complex per link
+  const size_t base = (size_t)p * 4 * ne * g.V2p + tix(s, 4 * ne) + mu * ne * kTile;
+  cpx<double> m[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    double2 v = zero ? make_double2(0.0, 0.0) : Uc[i * 9 + e];
+    const double2 v = zero ? make_double2(0.0, 0.0) : Uc[i * 9 + e];
+    m[e] = {v.x, v.y};
+  }
+  for (int e = 0; e < ne; ++e) {
     const size_t o = base + e * kTile;
-    U64[o] = v;
-    if (U32) st(U32 + o, cpx<double>{v.x, v.y});
-    if (U16) st(U16 + o, cpx<double>{v.x, v.y});
+    U64[o] = make_double2(m[e].re, m[e].im);
+    if (U32) st(U32 + o, m[e]);
+    if (U16) st(U16 + o, m[e]);
+  }
+  if (two_row) {
+    cpx<double> w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e] = m[e];
+    su3_third_row(w);
+    bool off = false;
+#pragma unroll
+    for (int e = 6; e < 9; ++e) off = off || !(hypot(w[e].re - m[e].re, w[e].im - m[e].im) <= 1e-10);
+    if (off) *bad = 1;  // every writer stores the same value
   }
 }
 
 hipError_t launch_import_gauge(const KGeom& g, const double2* Uc, double2* U64, float2* U32,
-                               bf16x2* U16, hipStream_t st) {
+                               bf16x2* U16, bool two_row, int* bad, hipStream_t st) {
+  if (two_row && !bad) return hipErrorInvalidValue;
   const long n = 4L * 2 * g.V2;
-  k_import_gauge<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, Uc, U64, U32, U16);
+  k_import_gauge<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, Uc, U64, U32, U16, two_row, bad);
   return hipGetLastError();
 }
 

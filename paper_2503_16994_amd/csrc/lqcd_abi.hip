@@ -112,13 +112,19 @@ extern "C" int64_t lqcd_geom_volume(const lqcd_geom_t* g) { return g ? g->V : 0;
 // ---------------------------------------------------------------------------
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-static size_t link_elems(const lqcd_geom_t* g) { return (size_t)2 * 36 * g->V2p; }
+// complex elements of one precision copy of the links: 4 directions x (9, or
+// 6 with two rows per link) per site, both parities
+static size_t link_elems(const lqcd_geom_t* g, int pmask) {
+  return (size_t)2 * 4 * ((pmask & LQCD_PM_TWO_ROW) ? 6 : 9) * g->V2p;
+}
 
 extern "C" size_t lqcd_gauge_bytes(const lqcd_geom_t* g, int pmask) {
   if (!g) return 0;
-  size_t b = align_up(link_elems(g) * 16);
-  if (pmask & LQCD_PM_F32) b += align_up(link_elems(g) * 8);
-  if (pmask & LQCD_PM_BF16) b += align_up(link_elems(g) * 4);
+  const size_t n = link_elems(g, pmask);
+  size_t b = align_up(n * 16);
+  if (pmask & LQCD_PM_F32) b += align_up(n * 8);
+  if (pmask & LQCD_PM_BF16) b += align_up(n * 4);
+  if (pmask & LQCD_PM_TWO_ROW) b += 256;  // flag of the SU(3) check
   return b;
 }
 
@@ -128,7 +134,7 @@ extern "C" int lqcd_gauge_create(const lqcd_geom_t* g, const void* U_dev, int pm
                                  size_t mem_bytes, void* stream, lqcd_gauge_t** out) {
   if (!g || !U_dev || !mem || !out) return fail(LQCD_EINVAL, "lqcd_gauge_create: null pointer");
   *out = nullptr;
-  if (pmask & ~7) return fail(LQCD_EINVAL, "lqcd_gauge_create: bad precision mask %d", pmask);
+  if (pmask & ~15) return fail(LQCD_EINVAL, "lqcd_gauge_create: bad precision mask %d", pmask);
   const size_t need = lqcd_gauge_bytes(g, pmask);
   if (mem_bytes < need)
     return fail(LQCD_ENOMEM, "lqcd_gauge_create: %zu bytes given, %zu needed", mem_bytes, need);
@@ -136,27 +142,43 @@ extern "C" int lqcd_gauge_create(const lqcd_geom_t* g, const void* U_dev, int pm
     return fail(LQCD_EINVAL, "lqcd_gauge_create: misaligned device pointer");
   lqcd_gauge* u = new (std::nothrow) lqcd_gauge;
   if (!u) return fail(LQCD_ENOMEM, "lqcd_gauge_create: host allocation failed");
+  const bool two_row = (pmask & LQCD_PM_TWO_ROW) != 0;
+  const size_t n = link_elems(g, pmask);
   char* p = (char*)mem;
   u->g = g;
   u->pmask = pmask | LQCD_PM_F64;
   u->uid = g_uid.fetch_add(1);
+  u->two_row = two_row ? 1 : 0;
   u->U64 = (double2*)p;
-  p += align_up(link_elems(g) * 16);
+  p += align_up(n * 16);
   u->U32 = nullptr;
   u->U16 = nullptr;
   if (pmask & LQCD_PM_F32) {
     u->U32 = (float2*)p;
-    p += align_up(link_elems(g) * 8);
+    p += align_up(n * 8);
   }
   if (pmask & LQCD_PM_BF16) {
     u->U16 = (bf16x2*)p;
-    p += align_up(link_elems(g) * 4);
+    p += align_up(n * 4);
   }
-  hipError_t e = launch_import_gauge(g->kg, (const double2*)U_dev, u->U64, u->U32, u->U16,
-                                     (hipStream_t)stream);
+  int* bad = two_row ? (int*)p : nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (bad) e = launch_fill_zero(bad, 256, st);
+  if (e == hipSuccess)
+    e = launch_import_gauge(g->kg, (const double2*)U_dev, u->U64, u->U32, u->U16, two_row, bad, st);
+  int h_bad = 0;
+  if (e == hipSuccess && bad) e = hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && bad) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete u;
     return hip_status(e, "gauge import");
+  }
+  if (h_bad) {
+    delete u;
+    return fail(LQCD_EINVAL,
+                "lqcd_gauge_create: LQCD_PM_TWO_ROW needs SU(3) links, but a third row differs from "
+                "conj(row0 x row1) by more than 1e-10");
   }
   *out = u;
   return LQCD_OK;
@@ -289,6 +311,7 @@ int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipS
   CloverLaunch c;
   c.g = w->g->kg;
   c.U64 = u->U64;
+  c.two_row = u->two_row;
   c.m0 = 1.0 / (2.0 * d->kappa) - 4.0;
   c.csw = d->csw;
   c.cF = d->cF;
@@ -351,6 +374,7 @@ static HopLaunch base_launch(const OpCtx& c) {
   h.g = c.w->g->kg;
   h.prec = h.in_prec = h.out_prec = c.prec;
   h.U = links_of(c.u, c.prec);
+  h.two_row = c.u->two_row;
   h.nrhs = c.nrhs;
   h.hop = true;
   apply_tuning(h, c.w->tune[c.prec]);
@@ -509,7 +533,8 @@ extern "C" int lqcd_ws_set_tuning(lqcd_ws_t* w, int prec, const lqcd_tuning* t) 
   if (!w || !t) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: null pointer");
   if (prec < 0 || prec > 2) return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: bad precision %d", prec);
   if (t->nr_tile < 1 || t->nr_tile > 3 || t->block_order < 0 || t->block_order > 6 ||
-      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE | (3 << LQCD_TUNE_OCC_SHIFT))))
+      (t->rhs_lanes != 1 && t->rhs_lanes != 2 && t->rhs_lanes != 4) || (t->flags & ~(LQCD_TUNE_NT_STORE | LQCD_TUNE_CACHED_GAUGE | (3 << LQCD_TUNE_OCC_SHIFT) |
+                     LQCD_TUNE_DIR_SPLIT)))
     return fail(LQCD_EINVAL, "lqcd_ws_set_tuning: value out of range");
   w->tune[prec] = *t;
   return LQCD_OK;
@@ -540,6 +565,7 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   LQCD_HIP(hipEventCreate(&e0));
   LQCD_HIP(hipEventCreate(&e1));
   const lqcd_tuning saved = w->tune[prec];
+  const int keep = saved.flags & LQCD_TUNE_DIR_SPLIT;  // the caller's choice
   double best_t = 1e300;
   lqcd_tuning best_cfg = saved;
   OpCtx c{u, w, prec, nrhs, st};
@@ -570,9 +596,10 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
     if (nrhs % rl || (prec == P_F64 && rl > 1)) continue;
     for (int nr = 1; nr <= 3 && err == hipSuccess; ++nr) {
       if (nrhs % (nr * rl)) continue;
+      if (keep && (nr != 1 || rl != 1)) continue;  // the split's shape only
       for (int cfg = 0; cfg < 28 && err == hipSuccess; ++cfg) {
         const int order = cfg >> 2;
-        const int flags = ((cfg & 1) ? LQCD_TUNE_NT_STORE : 0) | ((cfg & 2) ? LQCD_TUNE_CACHED_GAUGE : 0);
+        const int flags = ((cfg & 1) ? LQCD_TUNE_NT_STORE : 0) | ((cfg & 2) ? LQCD_TUNE_CACHED_GAUGE : 0) | keep;
         w->tune[prec] = lqcd_tuning{nr, order, rl, flags};
         trial();
       }

@@ -196,6 +196,20 @@ __device__ inline cpx<A> csub_i(cpx<A> a, cpx<A> b) { return {a.re + b.im, a.im 
 template <typename A>
 __device__ inline cpx<A> cscale(A s, cpx<A> a) { return {s * a.re, s * a.im}; }
 
+// Third row of an SU(3) matrix (row major, m[3 a + b]) from its first two.
+// For a unitary matrix of determinant one the inverse is both the adjoint
+// and the adjugate, so each entry of row 2 is the complex conjugate of its
+// cofactor: row 2 = conj(row 0 x row 1).
+template <typename A>
+__device__ inline void su3_third_row(cpx<A> (&m)[9]) {
+  const cpx<A> c0 = csub(cmul(m[1], m[5]), cmul(m[2], m[4]));
+  const cpx<A> c1 = csub(cmul(m[2], m[3]), cmul(m[0], m[5]));
+  const cpx<A> c2 = csub(cmul(m[0], m[4]), cmul(m[1], m[3]));
+  m[6] = {c0.re, -c0.im};
+  m[7] = {c1.re, -c1.im};
+  m[8] = {c2.re, -c2.im};
+}
+
 // ---------------------------------------------------------------------------
 // Fast unsigned division by a runtime constant (Granlund-Montgomery style):
 // q = (umulhi(n, m) + n) >> l  with l = ceil(log2 d), m = 2^32 (2^l - d)/d + 1,

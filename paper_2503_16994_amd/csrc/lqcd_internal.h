@@ -22,6 +22,7 @@ struct lqcd_gauge {
   const lqcd_geom_t* g;
   int pmask;
   uint64_t uid;  // distinguishes gauge fields for the clover cache
+  int two_row;   // links stored as their first two rows
   double2* U64;
   float2* U32;
   lqcd::bf16x2* U16;
@@ -125,6 +126,7 @@ inline void apply_tuning(HopLaunch& h, const lqcd_tuning& t) {
   h.nt_out = (t.flags & LQCD_TUNE_NT_STORE) ? 1 : 0;
   h.cached_gauge = (t.flags & LQCD_TUNE_CACHED_GAUGE) ? 1 : 0;
   h.occ_cap = (t.flags >> LQCD_TUNE_OCC_SHIFT) & 3;
+  h.dir_split = (t.flags & LQCD_TUNE_DIR_SPLIT) ? 1 : 0;  // used where nr_tile = rhs_lanes = 1
 }
 inline void single_tile(HopLaunch& h) {
   h.nr_tile = 1;

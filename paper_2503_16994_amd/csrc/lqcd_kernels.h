@@ -30,6 +30,7 @@ struct HopLaunch {
   int out_prec;   // storage precision of out
   int p_out;
   const void* U;     // links (both parities), precision prec
+  int two_row;       // links stored as their first two rows (6 of 9 complex)
   const void* y;     // opposite-parity input
   const void* z;     // same-parity input (PRE_IDENT / PRE_CLOV)
   const void* Cpre;  // clover blocks of parity p_out (tiled 36-component field)
@@ -59,6 +60,8 @@ struct HopLaunch {
   int cached_gauge;  // 1: ordinary (cached) loads of links and clover blocks
                      // instead of non-temporal ones (rhs tiles re-read them)
   int occ_cap;       // 0..3: cap on resident workgroups per CU (unused LDS)
+  int dir_split;     // 1: two waves per site block split the hop directions
+                     // (launches with nr_tile = rhs_lanes = 1 only)
   unsigned lds_cap;  // dynamic LDS bytes of the launch (set by the launcher)
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
@@ -87,9 +90,11 @@ hipError_t launch_hop(const HopLaunch& h, hipStream_t st);
 hipError_t launch_hop_xr(const HopLaunch& h, hipStream_t st);
 
 // Gauge import: canonical complex128 U -> internal links (any non-null
-// precision pointer is written); OPEN zeroes U_t(T-1).
+// precision pointer is written); OPEN zeroes U_t(T-1).  two_row: store the
+// first two rows only, and set *bad (zeroed by the caller) when a link's
+// third row differs from the rebuilt one by more than 1e-10.
 hipError_t launch_import_gauge(const KGeom& g, const double2* Ucanon, double2* U64, float2* U32,
-                               bf16x2* U16, hipStream_t st);
+                               bf16x2* U16, bool two_row, int* bad, hipStream_t st);
 
 // Spinor layout conversion.  Internal "full" vector: [rhs][parity][k][s].
 // pack: canonical [rhs][site][12] -> internal (g5 optional), precision prec.
@@ -103,6 +108,7 @@ hipError_t launch_unpack(const KGeom& g, const void* internal, int prec, double2
 struct CloverLaunch {
   KGeom g;
   const double2* U64;
+  int two_row;  // links stored as their first two rows (6 complex)
   double m0, csw, cF;
   double2* C64;     // two parities, each a tiled 36-component field
   double2* Ci64;    // tiled 36-component field: inverse on the odd sites

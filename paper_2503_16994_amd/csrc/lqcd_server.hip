@@ -280,7 +280,7 @@ extern "C" int lqcd_server_add_gauge(lqcd_server_t* s, const lqcd_geom_desc* des
                                      int pmask, int* gauge_id) {
   if (!s || !desc || !gauge_id || (!U_host && !s->sim))
     return fail(LQCD_EINVAL, "lqcd_server_add_gauge: null pointer");
-  if (pmask & ~7) return fail(LQCD_EINVAL, "lqcd_server_add_gauge: bad precision mask");
+  if (pmask & ~15) return fail(LQCD_EINVAL, "lqcd_server_add_gauge: bad precision mask");
   lqcd_geom_t* geom = nullptr;
   int rc = lqcd_geom(desc, &geom);
   if (rc) return rc;

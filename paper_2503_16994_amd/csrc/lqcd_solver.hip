@@ -78,6 +78,7 @@ HopLaunch mk(const Ctl& c, int lprec) {
   h.g = c.g->kg;
   h.prec = lprec;
   h.U = links_of(c.u, lprec);
+  h.two_row = c.u->two_row;
   h.nrhs = c.nrhs;
   h.hop = true;
   apply_tuning(h, c.w->tune[lprec]);

@@ -28,9 +28,13 @@ BC_PERIODIC, BC_SF, BC_OPEN = 0, 1, 2
 # precisions and masks
 F64, F32, BF16 = 0, 1, 2
 PM_F64, PM_F32, PM_BF16 = 1, 2, 4
+PM_PRECISIONS = PM_F64 | PM_F32 | PM_BF16
+# gauge fields only: links stored as their first two rows (SU(3) links only)
+PM_TWO_ROW = 8
 TUNE_NT_STORE = 1  # lqcd_tuning.flags: non-temporal output stores in the hop kernels
 TUNE_CACHED_GAUGE = 2  # lqcd_tuning.flags: cached (not non-temporal) link and clover loads
 TUNE_OCC_SHIFT = 2  # lqcd_tuning.flags bits 2-3: cap of resident workgroups per CU (4, 3, 2)
+TUNE_DIR_SPLIT = 16  # lqcd_tuning.flags: two waves per site block split the hop directions
 # operators
 (OP_DW, OP_DW_DAG, OP_G5DW, OP_DWDAGDW, OP_SCHUR, OP_SCHUR_DAG, OP_SCHUR_NORMAL, OP_HOP_EO,
  OP_HOP_OE) = range(9)
@@ -67,7 +71,7 @@ class Tuning(ctypes.Structure):
     def as_dict(self):
         return {"nr_tile": self.nr_tile, "block_order": self.block_order, "rhs_lanes": self.rhs_lanes,
                 "nt_store": bool(self.flags & TUNE_NT_STORE), "cached_gauge": bool(self.flags & TUNE_CACHED_GAUGE),
-                "occ_cap": (self.flags >> TUNE_OCC_SHIFT) & 3}
+                "occ_cap": (self.flags >> TUNE_OCC_SHIFT) & 3, "dir_split": bool(self.flags & TUNE_DIR_SPLIT)}
 
 
 class SolveInfo(ctypes.Structure):
@@ -187,7 +191,8 @@ class Lattice:
 
 
 class GaugeField:
-    """Device-resident gauge field (lqcd_gauge_create) in FP64 and `pmask` precisions."""
+    """Device-resident gauge field (lqcd_gauge_create) in FP64 and `pmask` precisions;
+    PM_TWO_ROW in `pmask` stores two rows per link (the field must be SU(3))."""
 
     def __init__(self, lat: Lattice, U, pmask=PM_F64, stream=None):
         self.lat = lat
@@ -249,7 +254,7 @@ def dw_apply(gauge: GaugeField, d: Dirac, psi: torch.Tensor, op=OP_DW, prec=F64,
     x = psi.reshape((-1,) + lat.spinor_shape()).contiguous()
     nrhs = x.shape[0]
     if ws is None:
-        ws = Workspace(lat, gauge.pmask, nrhs)
+        ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, nrhs)
     if out is None:
         out = torch.empty_like(x)
     _check(lib().lqcd_dw_apply(gauge.handle, ctypes.byref(d), op, prec, LAYOUT_CANON, nrhs,
@@ -267,10 +272,10 @@ def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torc
 
 
 def set_tuning(ws: Workspace, prec, nr_tile=1, block_order=1, rhs_lanes=1, nt_store=False, cached_gauge=False,
-               occ_cap=0):
+               occ_cap=0, dir_split=False):
     t = Tuning(int(nr_tile), int(block_order), int(rhs_lanes),
                (TUNE_NT_STORE if nt_store else 0) | (TUNE_CACHED_GAUGE if cached_gauge else 0)
-               | ((int(occ_cap) & 3) << TUNE_OCC_SHIFT))
+               | ((int(occ_cap) & 3) << TUNE_OCC_SHIFT) | (TUNE_DIR_SPLIT if dir_split else 0))
     _check(lib().lqcd_ws_set_tuning(ws.handle, prec, ctypes.byref(t)))
 
 
@@ -310,7 +315,7 @@ def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, m
     e = eta.reshape((-1,) + lat.spinor_shape()).contiguous()
     nrhs = e.shape[0]
     if ws is None:
-        ws = Workspace(lat, gauge.pmask, nrhs)
+        ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, nrhs)
     if psi is None:
         psi = torch.empty_like(e)
     p = SolveParams(Dirac(float(kappa), float(csw), float(cF), 0.0), solver, inner_prec,

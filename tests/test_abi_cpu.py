@@ -85,6 +85,12 @@ def test_geometry_sizes():
     assert lib.lqcd_vec_bytes(h, lqcd.F64, 1, 2) == 2 * 12 * 320 * 16
     assert lib.lqcd_vec_bytes(h, lqcd.F32, 3, 1) == 3 * 12 * 320 * 8
     assert lib.lqcd_gauge_bytes(h, lqcd.PM_F64) >= 2 * 36 * 320 * 16
+    # two rows per link: 24 instead of 36 complex per site and parity, plus
+    # the 256-byte flag of the SU(3) check
+    full = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_BF16)
+    two = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_BF16 | lqcd.PM_TWO_ROW)
+    assert two == 2 * 24 * 320 * 16 + 2 * 24 * 320 * 4 + 256
+    assert full == 2 * 36 * 320 * 16 + 2 * 36 * 320 * 4
     lib.lqcd_geom_free(h)
 
 
@@ -95,6 +101,12 @@ def test_null_and_bad_arguments_are_rejected_without_device_work():
     assert lib.lqcd_dw_apply(None, None, 0, 0, 0, 1, None, None, None, None) == lqcd.EINVAL
     assert lib.lqcd_solve(None, None, None, None, None, None, None) == lqcd.EINVAL
     assert lib.lqcd_gauge_create(None, None, 1, None, 0, None, ctypes.byref(h)) == lqcd.EINVAL
+    g = ctypes.c_void_p()
+    assert lib.lqcd_geom(ctypes.byref(_desc(lqcd, (4, 4, 4, 4))), ctypes.byref(g)) == lqcd.OK
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: the mask is rejected first
+    assert lib.lqcd_gauge_create(g, fake, 16, fake, 1 << 30, None, ctypes.byref(h)) == lqcd.EINVAL
+    assert b"precision mask" in lib.lqcd_last_error()
+    lib.lqcd_geom_free(g)
     assert lib.lqcd_ws_create(None, 1, 1, None, 0, ctypes.byref(h)) == lqcd.EINVAL
     assert lib.lqcd_strerror(lqcd.ENOCONV) == b"solver did not converge"
     t = lqcd.Tuning(1, 1, 0, 0)
@@ -119,8 +131,12 @@ def test_tuning_values_are_validated():
     back = lqcd.Tuning()
     assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK
     assert back.as_dict() == {"nr_tile": 2, "block_order": 4, "rhs_lanes": 2, "nt_store": True, "cached_gauge": False,
-                              "occ_cap": 0}
-    for bad in (lqcd.Tuning(4, 1, 1, 0), lqcd.Tuning(1, 7, 1, 0), lqcd.Tuning(1, 1, 3, 0), lqcd.Tuning(1, 1, 1, 16)):
+                              "occ_cap": 0, "dir_split": False}
+    split = lqcd.Tuning(1, 2, 1, lqcd.TUNE_DIR_SPLIT | lqcd.TUNE_CACHED_GAUGE)
+    assert lib.lqcd_ws_set_tuning(w, lqcd.F64, ctypes.byref(split)) == lqcd.OK
+    assert lib.lqcd_ws_get_tuning(w, lqcd.F64, ctypes.byref(back)) == lqcd.OK and back.as_dict()["dir_split"]
+    for bad in (lqcd.Tuning(4, 1, 1, 0), lqcd.Tuning(1, 7, 1, 0), lqcd.Tuning(1, 1, 3, 0), lqcd.Tuning(1, 1, 1, 32),
+                lqcd.Tuning(1, 1, 1, 64)):
         assert lib.lqcd_ws_set_tuning(w, lqcd.F32, ctypes.byref(bad)) == lqcd.EINVAL
     assert lib.lqcd_ws_set_tuning(w, 3, ctypes.byref(ok)) == lqcd.EINVAL
     assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK and back.flags == lqcd.TUNE_NT_STORE

@@ -381,3 +381,50 @@ def test_schur_identity_dense(bc):
     # Dhat is the Schur complement: its residual equals the full residual
     r_full = eta.reshape(-1) - M @ psi.reshape(-1)
     assert np.linalg.norm(r_full) < 1e-12 * np.linalg.norm(eta)
+
+
+# ---- two-row links (paper Sec. 2.2, SU(3) type) ------------------------------
+def test_two_row_rebuild_is_exact_for_su3():
+    """Haar-random U(3) matrices (QR, independent of the oracle) scaled to unit
+    determinant, and the generator's links: the third row rebuilt from the
+    first two matches to rounding, and the result is special unitary."""
+    rng = np.random.default_rng(31)
+    Q = haar_u3(rng, 500)
+    Q = Q / np.linalg.det(Q)[:, None, None] ** (1.0 / 3.0)
+    for M in (Q, inputs.gauge_field((4, 4, 4, 4), 0.3, seed=5).reshape(-1, 3, 3)):
+        R = orc.su3_from_two_rows(M[:, :2, :])
+        assert np.max(np.abs(R - M)) < 1e-14
+        assert np.allclose(R @ np.conj(np.swapaxes(R, -1, -2)), np.eye(3), atol=1e-14)
+        assert np.allclose(np.linalg.det(R), 1.0, atol=1e-14)
+
+
+def test_two_row_rebuild_of_a_u3_matrix_carries_the_determinant():
+    """Closed form off SU(3): for unitary M of determinant d the rebuilt row
+    is conj(d) times M's third row (a dropped conjugate, a swapped cross
+    product or a wrong cofactor sign fails this)."""
+    rng = np.random.default_rng(32)
+    M = haar_u3(rng, 200)
+    d = np.linalg.det(M)
+    assert np.max(np.abs(np.abs(d) - 1)) < 1e-12 and np.max(np.abs(d - 1)) > 0.1
+    R = orc.su3_from_two_rows(M[:, :2, :])
+    assert np.array_equal(R[:, :2, :], M[:, :2, :])
+    assert np.max(np.abs(R[:, 2, :] - np.conj(d)[:, None] * M[:, 2, :])) < 1e-14
+    # a diagonal phase matrix, by hand: rows (e^{ia},0,0), (0,e^{ib},0) give
+    # third row (0, 0, e^{-i(a+b)})
+    a, b = 0.7, -1.9
+    D = np.zeros((1, 2, 3), np.complex128)
+    D[0, 0, 0], D[0, 1, 1] = np.exp(1j * a), np.exp(1j * b)
+    assert np.allclose(orc.su3_from_two_rows(D)[0, 2], [0, 0, np.exp(-1j * (a + b))], atol=1e-15)
+
+
+@pytest.mark.parametrize("bc", [PERIODIC, SF, OPEN])
+def test_dw_is_unchanged_by_two_row_storage(bc):
+    """Storing two rows per link and rebuilding the third loses nothing for
+    SU(3) links: Dw from the rebuilt field equals Dw from the original."""
+    L = (4, 4, 4, 6)
+    U, A, theta = _setup(L, bc, seed=41)
+    U2 = orc.su3_from_two_rows(U[..., :2, :])
+    assert np.max(np.abs(U2 - U)) < 1e-14
+    psi = inputs.gaussian_spinor(L, 3, bc)
+    A2 = orc.clover_matrix(L, bc, U2, 0.05, 1.9, 1.0)
+    assert rel(orc.dw(L, bc, theta, U2, A2, psi), orc.dw(L, bc, theta, U, A, psi)) < 1e-14
