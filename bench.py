@@ -422,14 +422,29 @@ def c3_leg(stream, pm, gpm, no_mixed, mixed_leg):
     etap = torch.from_numpy(inputs.point_sources_12(L3, (0, 0, 0, 0))).cuda()
     lqcd.autotune(g3, d3, lqcd.F64, 1, ws3, stream=stream)
 
+    prop = torch.empty_like(etap)
+
     def f64_one():
         return [lqcd.solve(g3, etap[j:j + 1], kappa, CSW, tol=TOL, inner_prec=lqcd.F64, use_graph=True, ws=ws3,
-                           stream=stream).info[0] for j in range(12)]
+                           stream=stream, psi=prop[j:j + 1]).info[0] for j in range(12)]
     dt, infos = timed(f64_one, 1, 1)
     fp64 = 12 / dt
     c3["propagator_12"] = {"fp64_one_at_a_time": {"solves_per_s": round(fp64, 2), "ms_per_12": round(dt * 1e3, 1),
                                                   "iters": max(i["iters"] for i in infos),
                                                   "max_true_residual": max(i["true_residual"] for i in infos)}}
+    # meson two-point functions of that propagator (16 diagonal Gamma pairs)
+    pairs = [(m, m) for m in range(16)]
+    ms_meson = time_launches(lambda: lqcd.meson(lat3, prop, pairs, ws3, stream=stream), 10, stream)
+    C, _ = lqcd.meson(lat3, prop, pairs, ws3, want_G=False, stream=stream)
+    torch.cuda.synchronize()
+    mb = 12 * 12 * 16 * lat3.volume  # the propagator, read once
+    c3["propagator_12"]["meson"] = {"us": round(ms_meson * 1e3, 1), "alg_bytes": mb,
+                                    "GB/s": round(mb / (ms_meson * 1e-3) / 1e9, 1),
+                                    "frac": round(mb / (ms_meson * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "pion_t0_t1_tmid": [float(C[15, 0].real), float(C[15, 1].real),
+                                                        float(C[15, 32].real)]}
+    log(f"meson: {c3['propagator_12']['meson']}")
+    del prop, C
     del ws3
     torch.cuda.empty_cache()
     if not no_mixed:
@@ -556,7 +571,8 @@ def profile_kernels(stream):
     on two-row links: FP64 at 16^3x32 and at 32^3x64, FP32 and BF16 at
     32^3x64 (one rhs), and FP32 with 12 rhs at 32^3x64 (rhs tile 3); at
     16^3x32 in the benchmark step's tuning, at 32^3x64 with block order 2,
-    non-temporal stores and (one rhs) the direction split."""
+    non-temporal stores and (one rhs) the direction split; then 10 meson
+    contractions of a random 12-column field at 32^3x64."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -600,6 +616,15 @@ def profile_kernels(stream):
             torch.cuda.synchronize()
             log(f"profiled {L} prec {prec} nrhs {nrhs} tuning {tune}")
             del x, y
+        if big:  # meson contraction of a 12-column field, 16 diagonal pairs
+            shape = (12,) + lat.spinor_shape()
+            prop = torch.complex(torch.randn(shape, dtype=torch.float64, device="cuda"),
+                                 torch.randn(shape, dtype=torch.float64, device="cuda"))
+            for _ in range(10):
+                lqcd.meson(lat, prop, [(m, m) for m in range(16)], ws, want_G=False, stream=stream)
+            torch.cuda.synchronize()
+            log(f"profiled meson {L}")
+            del prop
         del g, ws
         torch.cuda.empty_cache()
 

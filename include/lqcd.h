@@ -183,6 +183,27 @@ int lqcd_dw_apply(const lqcd_gauge_t *u, const lqcd_dirac *d, int op, int prec, 
  * parities in precision prec. */
 size_t lqcd_vec_bytes(const lqcd_geom_t *g, int prec, int nrhs, int nparity);
 
+/* ---- meson two-point functions (paper Sec. 3.3: correlation functions
+ * contracted from the propagator) --------------------------------------- */
+/* From a 12-column point-source propagator psi (device, canonical
+ * complex128, 12 fields of V x 12, column j = 3 s + c for source spin s and
+ * colour c, e.g. the solution of the 12 point sources of lqcd_solve), with
+ * S(x)[al a][be c] = psi_(3 be + c)(x)[al][a]:
+ *   G (device complex128 [T][4][4][4][4], may be NULL):
+ *     G[t][al][be][al'][be'] = sum_{x in slice t} sum_{a,c} S(x)[al a][be c] conj(S(x)[al' a][be' c]);
+ *   C (device complex128 [npairs][T]): for each pair (m, m') of `pairs`
+ *     (host, npairs x 2 masks 0..15),
+ *     C[p][t] = sum_{x in slice t} tr[Gamma_m S(x) Gamma_m' g5 S(x)^+ g5],
+ *     the meson correlator with the backward propagator g5 S^+ g5 (no
+ *     fermion-loop sign), Gamma_m = g_t^{m3} g_x^{m0} g_y^{m1} g_z^{m2} in
+ *     the chiral basis (m = 0: identity, 15: g5, 8: g_t, 1/2/4: g_x/y/z).
+ * npairs 0..32 (C and pairs unused for 0); at least one of C and G.  The
+ * workspace w (same geometry, any precisions, any nrhs) provides scratch;
+ * its vectors are overwritten.  FP64, deterministic (fixed-order sums).
+ * EINVAL for bad arguments, without device work. */
+int lqcd_meson(const lqcd_geom_t *g, const void *psi, int npairs, const int32_t *pairs, void *C, void *G,
+               lqcd_ws_t *w, void *stream);
+
 /* ---- kernel tuning (autotuner) ------------------------------------------ */
 typedef struct lqcd_tuning {
   int32_t nr_tile;     /* right-hand sides per thread in the hop kernels: 1..3

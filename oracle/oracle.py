@@ -19,7 +19,8 @@ Sheikholeslami-Wohlert operator the paper cites):
 
 Functions with a pin in ``tests/test_oracle_pins.py``: ``gamma``,
 ``field_strength``, ``clover_matrix``, ``hop``, ``dw``, ``dw_dag``, ``cg``,
-``schur_*``, ``su3_from_two_rows``.  None is "parity unpinned".
+``schur_*``, ``su3_from_two_rows``, ``gamma_product``, ``meson_G``,
+``meson_correlator``.  None is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -265,6 +266,36 @@ def su3_from_two_rows(U2) -> np.ndarray:
     r0, r1 = U2[..., 0, :], U2[..., 1, :]
     r2 = np.conj(np.cross(r0, r1))
     return np.stack([r0, r1, r2], axis=-2)
+
+
+def gamma_product(mask: int) -> np.ndarray:
+    """Gamma_m = g_t^{m3} g_x^{m0} g_y^{m1} g_z^{m2}, the ordered product with
+    g_t first (mask 15 is g5 = g_t g_x g_y g_z, 0 the identity)."""
+    out = np.eye(4, dtype=np.complex128)
+    for mu in (3, 0, 1, 2):
+        if (mask >> mu) & 1:
+            out = out @ gamma(mu)
+    return out
+
+
+def meson_G(L, psi12) -> np.ndarray:
+    """Colour-traced spin tensor of a 12-column point-source propagator per
+    time slice (paper Sec. 3.3: correlators contracted from propagators):
+    G[t, al, be, al', be'] = sum_{x in slice t} sum_{a, c} S(x)[al a][be c] conj(S(x)[al' a][be' c]),
+    with S(x)[al a][be c] = psi12[3 be + c][x][al][a] (column 3 s + c: source
+    spin s, colour c)."""
+    Lx, Ly, Lz, T = L
+    P = np.asarray(psi12, np.complex128).reshape(4, 3, T, Lz * Ly * Lx, 4, 3)  # [be, c, t, x, al, a]
+    return np.einsum("bctxAa,dctxBa->tAbBd", P, P.conj())
+
+
+def meson_correlator(G, m1: int, m2: int) -> np.ndarray:
+    """C[t] = sum_x tr[Gamma_m1 S(x) Gamma_m2 g5 S(x)^+ g5] (backward
+    propagator from g5-hermiticity), written with G:
+    sum Gamma[de][al] Gamma'[be][ga] g5[ga] g5[de] G[t][al][be][de][ga]."""
+    A, B = gamma_product(m1), gamma_product(m2)
+    g5 = np.diag(gamma(4)).real
+    return np.einsum("da,bg,g,d,tabdg->t", A, B, g5, g5, G)
 
 
 def dense_dw(L, bc, theta, U, A) -> np.ndarray:

@@ -96,6 +96,15 @@ hipError_t launch_hop_xr(const HopLaunch& h, hipStream_t st);
 hipError_t launch_import_gauge(const KGeom& g, const double2* Ucanon, double2* U64, float2* U32,
                                bf16x2* U16, bool two_row, int* bad, hipStream_t st);
 
+// Meson two-point functions (k_meson.hip): colour-traced spin tensor G per
+// time slice of a 12-column canonical propagator (G may be null) and the
+// correlators of up to kMaxMesonPairs (Gamma, Gamma') mask pairs into C
+// ([pair][t]); scratch holds T x meson_nchunk(V3) x 256 complex partials.
+constexpr int kMaxMesonPairs = 32;
+int meson_nchunk(long V3);
+hipError_t launch_meson(const KGeom& g, const double2* psi, int npairs, const int* masks, double2* C,
+                        double2* G, double2* scratch, hipStream_t st);
+
 // Spinor layout conversion.  Internal "full" vector: [rhs][parity][k][s].
 // pack: canonical [rhs][site][12] -> internal (g5 optional), precision prec.
 hipError_t launch_pack(const KGeom& g, const double2* canon, void* internal, int prec, int nrhs,

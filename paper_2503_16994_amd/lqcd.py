@@ -104,6 +104,7 @@ SIGNATURES = {
     "lqcd_dw_apply": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _I, _I, _P, _P, _P, _P]),
     "lqcd_vec_bytes": (_Z, [_P, _I, _I, _I]),
     "lqcd_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
+    "lqcd_meson": (_I, [_P, _P, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
     "lqcd_ws_set_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
     "lqcd_ws_get_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
     "lqcd_autotune": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _P, _P, ctypes.POINTER(Tuning),
@@ -327,6 +328,28 @@ def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, m
         _check(st)
     out = psi[0] if single else psi
     return SolveResult(out, [infos[i].as_dict() for i in range(nrhs)], st)
+
+
+# gamma-matrix masks of lqcd_meson: Gamma_m = g_t^{m3} g_x^{m0} g_y^{m1} g_z^{m2}
+GAMMA_1, GAMMA_X, GAMMA_Y, GAMMA_Z, GAMMA_T, GAMMA_5 = 0, 1, 2, 4, 8, 15
+
+
+def meson(lat: Lattice, psi: torch.Tensor, pairs, ws: Workspace, want_G=True, stream=None):
+    """lqcd_meson on a 12-column canonical propagator ``psi`` (device,
+    complex128, shape (12, T, Z, Y, X, 4, 3)): returns (C, G) with C of shape
+    (len(pairs), T) and G of shape (T, 4, 4, 4, 4) (None unless want_G)."""
+    p = psi.contiguous()
+    if p.dtype != torch.complex128 or p.numel() != 12 * lat.volume * 12:
+        raise ValueError("psi must be 12 canonical complex128 fields")
+    T = lat.L[3]
+    n = len(pairs)
+    flat = (ctypes.c_int32 * max(2 * n, 1))(*[int(m) for pr in pairs for m in pr])
+    C = torch.empty((n, T), dtype=torch.complex128, device=p.device) if n else None
+    G = torch.empty((T, 4, 4, 4, 4), dtype=torch.complex128, device=p.device) if want_G else None
+    _check(lib().lqcd_meson(lat.handle, ctypes.c_void_p(p.data_ptr()), n, flat,
+                            ctypes.c_void_p(C.data_ptr() if C is not None else 0),
+                            ctypes.c_void_p(G.data_ptr() if G is not None else 0), ws.handle, _stream_ptr(stream)))
+    return C, G
 
 
 class Server:

@@ -140,5 +140,13 @@ def test_tuning_values_are_validated():
         assert lib.lqcd_ws_set_tuning(w, lqcd.F32, ctypes.byref(bad)) == lqcd.EINVAL
     assert lib.lqcd_ws_set_tuning(w, 3, ctypes.byref(ok)) == lqcd.EINVAL
     assert lib.lqcd_ws_get_tuning(w, lqcd.F32, ctypes.byref(back)) == lqcd.OK and back.flags == lqcd.TUNE_NT_STORE
+    # meson contraction: argument checks before any device work
+    pairs = (ctypes.c_int32 * 4)(15, 15, 16, 0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.lqcd_meson(g, fake, 33, pairs, fake, None, w, None) == lqcd.EINVAL
+    assert lib.lqcd_meson(g, fake, 2, pairs, fake, None, w, None) == lqcd.EINVAL  # mask 16
+    assert b"gamma mask" in lib.lqcd_last_error()
+    assert lib.lqcd_meson(g, fake, 0, None, None, None, w, None) == lqcd.EINVAL  # nothing to compute
+    assert lib.lqcd_meson(g, None, 1, pairs, fake, None, w, None) == lqcd.EINVAL
     lib.lqcd_ws_free(w)
     lib.lqcd_geom_free(g)

@@ -428,3 +428,87 @@ def test_dw_is_unchanged_by_two_row_storage(bc):
     psi = inputs.gaussian_spinor(L, 3, bc)
     A2 = orc.clover_matrix(L, bc, U2, 0.05, 1.9, 1.0)
     assert rel(orc.dw(L, bc, theta, U2, A2, psi), orc.dw(L, bc, theta, U, A, psi)) < 1e-14
+
+
+# ---- meson two-point functions ------------------------------------------------
+def test_gamma_products_are_the_sixteen_clifford_elements():
+    """The 16 ordered products are the Clifford basis: mask 15 is g5, each
+    squares to +-1 and tr(Gamma_a^+ Gamma_b) = 4 delta_ab."""
+    Gs = [orc.gamma_product(m) for m in range(16)]
+    assert np.allclose(Gs[15], G5) and np.allclose(Gs[0], np.eye(4))
+    for mu, m in ((0, 1), (1, 2), (2, 4), (3, 8)):
+        assert np.array_equal(Gs[m], GAM[mu])
+    assert np.allclose(Gs[8 | 1], GAM[3] @ GAM[0])  # t first
+    for a in range(16):
+        sq = Gs[a] @ Gs[a]
+        assert np.allclose(sq, np.eye(4)) or np.allclose(sq, -np.eye(4))
+        for b in range(16):
+            assert abs(np.trace(Gs[a].conj().T @ Gs[b]) - 4.0 * (a == b)) < 1e-14
+
+
+def _propagator_matrix(L, psi12, x):
+    """S(x) as a 12x12 matrix, rows (al, a), columns (be, c), by loops."""
+    Lx, Ly, Lz, T = L
+    t, rem = divmod(x, Lx * Ly * Lz)
+    z, rem = divmod(rem, Lx * Ly)
+    y, xx = divmod(rem, Lx)
+    S = np.zeros((12, 12), np.complex128)
+    for be in range(4):
+        for c in range(3):
+            for al in range(4):
+                for a in range(3):
+                    S[3 * al + a, 3 * be + c] = psi12[3 * be + c, t, z, y, xx, al, a]
+    return S
+
+
+def test_meson_correlators_against_explicit_traces():
+    """Brute force on a 2x2x2x4 lattice with a random 12-column field: every
+    (Gamma, Gamma') correlator from G equals the explicit per-site trace
+    tr[Gamma S Gamma' g5 S^+ g5] with 12x12 matrices (independent route: no
+    index contraction)."""
+    L = (2, 2, 2, 4)
+    rng = np.random.default_rng(61)
+    psi = rng.standard_normal((12, 4, 2, 2, 2, 4, 3)) + 1j * rng.standard_normal((12, 4, 2, 2, 2, 4, 3))
+    G = orc.meson_G(L, psi)
+    g5 = np.kron(G5, np.eye(3))
+    Ss = [_propagator_matrix(L, psi, x) for x in range(32)]
+    for m1 in range(16):
+        for m2 in (0, 1, 8, 15, m1):
+            A = np.kron(orc.gamma_product(m1), np.eye(3))
+            B = np.kron(orc.gamma_product(m2), np.eye(3))
+            brute = np.zeros(4, np.complex128)
+            for x, S in enumerate(Ss):
+                brute[x // 8] += np.trace(A @ S @ B @ g5 @ S.conj().T @ g5)
+            assert np.allclose(orc.meson_correlator(G, m1, m2), brute, rtol=1e-13, atol=1e-12)
+
+
+def test_pion_correlator_is_the_summed_norm():
+    """C(g5, g5)(t) = sum over the slice of |psi|^2 over all columns."""
+    L = (4, 2, 2, 6)
+    rng = np.random.default_rng(62)
+    psi = rng.standard_normal((12, 6, 2, 2, 4, 4, 3)) + 1j * rng.standard_normal((12, 6, 2, 2, 4, 4, 3))
+    C = orc.meson_correlator(orc.meson_G(L, psi), 15, 15)
+    direct = np.sum(np.abs(psi) ** 2, axis=(0, 2, 3, 4, 5, 6))
+    assert np.allclose(C.real, direct, rtol=1e-13) and np.max(np.abs(C.imag)) < 1e-12 * np.max(direct)
+
+
+def test_free_meson_correlators_time_reversal_and_cubic_symmetry():
+    """Free field (U = 1), point source at the origin, 4^3x8 antiperiodic in
+    time: the pion correlator is positive and symmetric under t -> T - t, and
+    the three vector correlators g_k g_k coincide (cubic symmetry)."""
+    L = (4, 4, 4, 8)
+    U = inputs.unit_gauge(L)
+    A = orc.clover_matrix(L, PERIODIC, U, orc.m0_from_kappa(0.12), 1.0)
+    th = (1, 1, 1, -1)
+    cols = []
+    for j in range(12):
+        eta = inputs.point_source(L, (0, 0, 0, 0), j // 3, j % 3)
+        x, rho, _, ok = orc.cg(L, PERIODIC, th, U, A, eta, tol=1e-12)
+        assert ok
+        cols.append(x)
+    G = orc.meson_G(L, np.stack(cols))
+    pi = orc.meson_correlator(G, 15, 15).real
+    assert np.all(pi > 0)
+    assert np.allclose(pi[1:], pi[1:][::-1], rtol=1e-9)
+    vk = [orc.meson_correlator(G, m, m) for m in (1, 2, 4)]
+    assert np.allclose(vk[0], vk[1], rtol=1e-9) and np.allclose(vk[0], vk[2], rtol=1e-9)
