@@ -376,7 +376,21 @@ def c4_leg(stream, pm, gpm, mixed_leg, steps):
     torch.cuda.empty_cache()
     ws12 = lqcd.Workspace(lat4, pm, 12)
     out["multi_rhs_12"] = mixed_leg(g4, lat4, ws12, eta4, kappa, csw, fp64, steps, 1, "24^3x48 SF")
-    del ws12, g4
+    del eta4
+    # f_P, f_A: boundary source, 12-rhs FP64 solve, contraction (one call)
+    t0 = time.perf_counter()
+    fP, fA, H, infos = lqcd.sf_correlators(g4, kappa, csw, tol=TOL, inner_prec=lqcd.F64, use_graph=True,
+                                           ws=ws12, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fP, fA = fP.real.cpu().numpy(), fA.real.cpu().numpy()
+    out["sf_correlators"] = {"seconds": round(dt, 3), "iters": max(i["iters"] for i in infos),
+                             "max_true_residual": max(i["true_residual"] for i in infos),
+                             "x0": [1, 2, 12, 24, 36, 47],
+                             "f_P": [float(fP[t]) for t in (1, 2, 12, 24, 36, 47)],
+                             "f_A": [float(fA[t]) for t in (1, 2, 12, 24, 36, 47)]}
+    log(f"SF f_P/f_A: {out['sf_correlators']}")
+    del ws12, g4, H
     torch.cuda.empty_cache()
     return out
 

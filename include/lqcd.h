@@ -308,6 +308,29 @@ typedef struct lqcd_solve_info {
 int lqcd_solve(const lqcd_gauge_t *u, const lqcd_solve_params *p, const void *eta,
                void *psi, lqcd_ws_t *w, void *stream, lqcd_solve_info *info);
 
+/* ---- Schroedinger functional: boundary-to-bulk propagator, f_P and f_A
+ * (paper Sec. 3.3: boundary-to-bulk propagators for Dirichlet boundary
+ * conditions and the correlators f_P, f_A) ------------------------------ */
+/* Boundary source: eta (device, canonical complex128, 12 fields of V x 12)
+ * is overwritten with the 12 columns (s, c) of P+ U_t(y0 = 0, y)^+ on the
+ * slice y0 = 1 (zero elsewhere), P+ = (1 + g_t)/2:
+ *   eta_{3s+c}(y)[al][a] = P+[al][s] conj(U_t(0, y)[c][a]).
+ * EINVAL unless u has SF boundary conditions. */
+int lqcd_sf_source(const lqcd_gauge_t *u, void *eta, void *stream);
+
+/* f_P(x0) = 1/2 sum_x tr[H(x)^+ H(x)] and f_A(x0) = -1/2 sum_x tr[H(x)^+ g_t H(x)]
+ * of the boundary-to-bulk propagator H = Dw^{-1} eta (eta from
+ * lqcd_sf_source), for x0 = 0..T-1.  Runs lqcd_sf_source into `eta`, the
+ * 12-rhs solve of `p` (p->nrhs is taken as 12; solver, precision and
+ * tolerance as given) into `psi` (= H on return, canonical, 12 x V x 12),
+ * then the meson contraction: fP and fA are device complex128 [T] (real
+ * parts; imaginary parts zero to rounding).  w: workspace with nrhs >= 12.
+ * info: 12 entries.  Returns the solve's status (fP, fA are written only on
+ * LQCD_OK). */
+int lqcd_sf_correlators(const lqcd_gauge_t *u, const lqcd_solve_params *p, void *eta, void *psi, void *fP,
+                        void *fA, lqcd_ws_t *w, void *stream, lqcd_solve_info *info);
+
+
 /* ---- serving: continuous batching of propagator solves ------------------ */
 /* A server keeps gauge fields resident in a caller-provided device arena and
  * runs solve requests as they arrive.  `max_streams` worker threads, each with

@@ -20,7 +20,8 @@ Sheikholeslami-Wohlert operator the paper cites):
 Functions with a pin in ``tests/test_oracle_pins.py``: ``gamma``,
 ``field_strength``, ``clover_matrix``, ``hop``, ``dw``, ``dw_dag``, ``cg``,
 ``schur_*``, ``su3_from_two_rows``, ``gamma_product``, ``meson_G``,
-``meson_correlator``.  None is "parity unpinned".
+``meson_correlator``, ``sf_source``, ``sf_correlators``.  None is "parity
+unpinned".
 """
 from __future__ import annotations
 
@@ -296,6 +297,32 @@ def meson_correlator(G, m1: int, m2: int) -> np.ndarray:
     A, B = gamma_product(m1), gamma_product(m2)
     g5 = np.diag(gamma(4)).real
     return np.einsum("da,bg,g,d,tabdg->t", A, B, g5, g5, G)
+
+
+def sf_source(L, U) -> np.ndarray:
+    """Boundary source of the Schroedinger-functional boundary-to-bulk
+    propagator (paper Sec. 3.3): the 12 columns (s, c) of P+ U_t(0, y)^+ on
+    the slice y0 = 1, P+ = (1 + g_t)/2, i.e.
+    eta_{3s+c}(y)[al][a] = delta_{y0,1} P+[al][s] conj(U_t(y0 = 0, y)[c][a])."""
+    Lx, Ly, Lz, T = L
+    Pp = (np.eye(4) + gamma(3)) / 2
+    eta = np.zeros((12, T, Lz, Ly, Lx, 4, 3), np.complex128)
+    Ut0 = np.asarray(U)[0, :, :, :, 3]  # [z, y, x, c, a]: the link from y0 = 0 to y0 = 1
+    for s in range(4):
+        for c in range(3):
+            eta[3 * s + c, 1] = Pp[:, s][None, None, None, :, None] * np.conj(Ut0[:, :, :, c, :])[:, :, :, None, :]
+    return eta
+
+
+def sf_correlators(L, H):
+    """f_P(x0) = 1/2 sum_x tr[H(x)^+ H(x)] and f_A(x0) = -1/2 sum_x tr[H(x)^+ g_t H(x)]
+    of the boundary-to-bulk propagator H (12 columns, H(x)[al a][s c] =
+    H_{3s+c}(x)[al][a], the solution for `sf_source`)."""
+    Lx, Ly, Lz, T = L
+    Hm = np.asarray(H, np.complex128).reshape(12, T, Lx * Ly * Lz, 4, 3)  # [col, t, x, al, a]
+    fP = 0.5 * np.einsum("jtxAa,jtxAa->t", Hm.conj(), Hm)
+    fA = -0.5 * np.einsum("jtxAa,AB,jtxBa->t", Hm.conj(), gamma(3), Hm)
+    return fP, fA
 
 
 def dense_dw(L, bc, theta, U, A) -> np.ndarray:

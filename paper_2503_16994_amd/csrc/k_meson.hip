@@ -153,10 +153,12 @@ __device__ inline cd gamma_entry(int m, int r, int c) {
 struct MesonPairs {
   int n;
   int m[kMaxMesonPairs][2];
+  double scale;                   // applied to every correlator
+  double2* out[kMaxMesonPairs];   // correlator of pair p: out[p][t]
 };
 
-__global__ __launch_bounds__(256) void k_meson_reduce(const double2* __restrict__ partials, int nchunk, int T,
-                                                      double2* G, double2* C, MesonPairs pairs) {
+__global__ __launch_bounds__(256) void k_meson_reduce(const double2* __restrict__ partials, int nchunk, double2* G,
+                                                      MesonPairs pairs) {
   __shared__ double red[2][4];
   const int t = blockIdx.x, i = threadIdx.x;
   double2 g = make_double2(0.0, 0.0);
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(256) void k_meson_reduce(const double2* __restrict_
         sr += red[0][ww];
         si += red[1][ww];
       }
-      C[(size_t)p * T + t] = make_double2(sr, si);
+      pairs.out[p][t] = make_double2(pairs.scale * sr, pairs.scale * si);
     }
     __syncthreads();
   }
@@ -199,21 +201,23 @@ __global__ __launch_bounds__(256) void k_meson_reduce(const double2* __restrict_
 
 int meson_nchunk(long V3) { return (int)((V3 + kMesonChunk - 1) / kMesonChunk); }
 
-hipError_t launch_meson(const KGeom& g, const double2* psi, int npairs, const int* masks, double2* C,
-                        double2* G, double2* scratch, hipStream_t st) {
+hipError_t launch_meson(const KGeom& g, const double2* psi, int npairs, const int* masks, double2* const* outs,
+                        double scale, double2* G, double2* scratch, hipStream_t st) {
   if (npairs < 0 || npairs > kMaxMesonPairs) return hipErrorInvalidValue;
   const long V3 = (long)g.L[0] * g.L[1] * g.L[2], V = V3 * g.L[3];
   const int nchunk = meson_nchunk(V3);
   MesonPairs pairs;
   pairs.n = npairs;
+  pairs.scale = scale;
   for (int p = 0; p < kMaxMesonPairs; ++p) {
     pairs.m[p][0] = p < npairs ? masks[2 * p] : 0;
     pairs.m[p][1] = p < npairs ? masks[2 * p + 1] : 0;
+    pairs.out[p] = p < npairs ? outs[p] : nullptr;
   }
   k_meson_partial<<<dim3(nchunk, g.L[3]), kMesonBlock, 0, st>>>(psi, V, V3, nchunk, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_meson_reduce<<<g.L[3], 256, 0, st>>>(scratch, nchunk, g.L[3], G, C, pairs);
+  k_meson_reduce<<<g.L[3], 256, 0, st>>>(scratch, nchunk, G, pairs);
   return hipGetLastError();
 }
 

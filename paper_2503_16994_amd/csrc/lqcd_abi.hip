@@ -546,8 +546,44 @@ extern "C" int lqcd_meson(const lqcd_geom_t* g, const void* psi, int npairs, con
   const size_t need = (size_t)g->desc.L[3] * meson_nchunk(V3) * 256 * sizeof(double2);
   const size_t have = (size_t)8 * w->nrhs * 24 * g->V2p * sizeof(double2);  // the FP64 vectors E..EH
   if (need > have) return fail(LQCD_EINVAL, "lqcd_meson: workspace scratch %zu < %zu bytes", have, need);
-  LQCD_HIP(launch_meson(g->kg, (const double2*)psi, npairs, pairs, (double2*)C, (double2*)G, w->m.E,
+  double2* outs[kMaxMesonPairs];
+  for (int p = 0; p < npairs; ++p) outs[p] = (double2*)C + (size_t)p * g->desc.L[3];
+  LQCD_HIP(launch_meson(g->kg, (const double2*)psi, npairs, pairs, outs, 1.0, (double2*)G, w->m.E,
                         (hipStream_t)stream));
+  return LQCD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Schroedinger functional: boundary source and f_P, f_A
+// ---------------------------------------------------------------------------
+extern "C" int lqcd_sf_source(const lqcd_gauge_t* u, void* eta, void* stream) {
+  if (!u || !eta) return fail(LQCD_EINVAL, "lqcd_sf_source: null pointer");
+  const lqcd_geom_t* g = u->g;
+  if (g->desc.bc != LQCD_BC_SF) return fail(LQCD_EINVAL, "lqcd_sf_source: the gauge field is not SF");
+  if ((uintptr_t)eta & 15) return fail(LQCD_EINVAL, "lqcd_sf_source: misaligned device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  LQCD_HIP(launch_fill_zero(eta, (size_t)12 * g->V * 12 * sizeof(double2), st));
+  LQCD_HIP(launch_sf_source(g->kg, u->U64, u->two_row, (double2*)eta, st));
+  return LQCD_OK;
+}
+
+extern "C" int lqcd_sf_correlators(const lqcd_gauge_t* u, const lqcd_solve_params* prm, void* eta, void* psi,
+                                   void* fP, void* fA, lqcd_ws_t* w, void* stream, lqcd_solve_info* info) {
+  if (!u || !prm || !eta || !psi || !fP || !fA || !w || !info)
+    return fail(LQCD_EINVAL, "lqcd_sf_correlators: null pointer");
+  if (w->nrhs < 12) return fail(LQCD_EINVAL, "lqcd_sf_correlators: workspace for %d < 12 rhs", w->nrhs);
+  if (((uintptr_t)fP & 15) || ((uintptr_t)fA & 15))
+    return fail(LQCD_EINVAL, "lqcd_sf_correlators: misaligned device pointer");
+  int rc = lqcd_sf_source(u, eta, stream);
+  if (rc) return rc;
+  lqcd_solve_params p12 = *prm;
+  p12.nrhs = 12;
+  rc = lqcd_solve(u, &p12, eta, psi, w, stream, info);
+  if (rc) return rc;
+  // f_P = 1/2 C(g5, g5), f_A = -1/2 C(g5 g_t, g5) = 1/2 C(Gamma_7, g5)
+  const int32_t pairs[4] = {15, 15, 7, 15};
+  double2* outs[2] = {(double2*)fP, (double2*)fA};
+  LQCD_HIP(launch_meson(u->g->kg, (const double2*)psi, 2, pairs, outs, 0.5, nullptr, w->m.E, (hipStream_t)stream));
   return LQCD_OK;
 }
 

@@ -98,12 +98,16 @@ hipError_t launch_import_gauge(const KGeom& g, const double2* Ucanon, double2* U
 
 // Meson two-point functions (k_meson.hip): colour-traced spin tensor G per
 // time slice of a 12-column canonical propagator (G may be null) and the
-// correlators of up to kMaxMesonPairs (Gamma, Gamma') mask pairs into C
-// ([pair][t]); scratch holds T x meson_nchunk(V3) x 256 complex partials.
+// correlators of up to kMaxMesonPairs (Gamma, Gamma') mask pairs, times
+// `scale`, into outs[p][t]; scratch holds T x meson_nchunk(V3) x 256
+// complex partials.
 constexpr int kMaxMesonPairs = 32;
 int meson_nchunk(long V3);
-hipError_t launch_meson(const KGeom& g, const double2* psi, int npairs, const int* masks, double2* C,
-                        double2* G, double2* scratch, hipStream_t st);
+hipError_t launch_meson(const KGeom& g, const double2* psi, int npairs, const int* masks, double2* const* outs,
+                        double scale, double2* G, double2* scratch, hipStream_t st);
+// SF boundary source (k_sf.hip): writes the slice y0 = 1 of the 12-column
+// canonical field eta (the rest must be zero) from the FP64 links
+hipError_t launch_sf_source(const KGeom& g, const double2* U64, int two_row, double2* eta, hipStream_t st);
 
 // Spinor layout conversion.  Internal "full" vector: [rhs][parity][k][s].
 // pack: canonical [rhs][site][12] -> internal (g5 optional), precision prec.

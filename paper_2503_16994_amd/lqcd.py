@@ -105,6 +105,8 @@ SIGNATURES = {
     "lqcd_vec_bytes": (_Z, [_P, _I, _I, _I]),
     "lqcd_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "lqcd_meson": (_I, [_P, _P, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
+    "lqcd_sf_source": (_I, [_P, _P, _P]),
+    "lqcd_sf_correlators": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "lqcd_ws_set_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
     "lqcd_ws_get_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
     "lqcd_autotune": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _P, _P, ctypes.POINTER(Tuning),
@@ -350,6 +352,33 @@ def meson(lat: Lattice, psi: torch.Tensor, pairs, ws: Workspace, want_G=True, st
                             ctypes.c_void_p(C.data_ptr() if C is not None else 0),
                             ctypes.c_void_p(G.data_ptr() if G is not None else 0), ws.handle, _stream_ptr(stream)))
     return C, G
+
+
+def sf_source(gauge: GaugeField, stream=None) -> torch.Tensor:
+    """lqcd_sf_source: the 12-column SF boundary source, canonical (12, T, Z, Y, X, 4, 3)."""
+    eta = torch.empty((12,) + gauge.lat.spinor_shape(), dtype=torch.complex128, device="cuda")
+    _check(lib().lqcd_sf_source(gauge.handle, ctypes.c_void_p(eta.data_ptr()), _stream_ptr(stream)))
+    return eta
+
+
+def sf_correlators(gauge: GaugeField, kappa, csw, cF=1.0, tol=1e-10, maxiter=20000, inner_prec=F64,
+                   reliable_every=100, use_graph=False, ws=None, stream=None):
+    """lqcd_sf_correlators: returns (fP, fA, H, infos) with fP, fA complex128 (T,)."""
+    lat = gauge.lat
+    if ws is None:
+        ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, 12)
+    shape = (12,) + lat.spinor_shape()
+    eta = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    H = torch.empty_like(eta)
+    fP = torch.empty(lat.L[3], dtype=torch.complex128, device="cuda")
+    fA = torch.empty_like(fP)
+    p = SolveParams(Dirac(float(kappa), float(csw), float(cF), 0.0), SOLVER_CG_EO, inner_prec,
+                    int(reliable_every), int(maxiter), float(tol), 12, int(bool(use_graph)))
+    infos = (SolveInfo * 12)()
+    _check(lib().lqcd_sf_correlators(gauge.handle, ctypes.byref(p), ctypes.c_void_p(eta.data_ptr()),
+                                     ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(fP.data_ptr()),
+                                     ctypes.c_void_p(fA.data_ptr()), ws.handle, _stream_ptr(stream), infos))
+    return fP, fA, H, [infos[i].as_dict() for i in range(12)]
 
 
 class Server:

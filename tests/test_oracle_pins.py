@@ -512,3 +512,61 @@ def test_free_meson_correlators_time_reversal_and_cubic_symmetry():
     assert np.allclose(pi[1:], pi[1:][::-1], rtol=1e-9)
     vk = [orc.meson_correlator(G, m, m) for m in (1, 2, 4)]
     assert np.allclose(vk[0], vk[1], rtol=1e-9) and np.allclose(vk[0], vk[2], rtol=1e-9)
+
+
+# ---- SF boundary-to-bulk propagator and f_P, f_A -------------------------------
+def test_sf_source_structure():
+    """Support on y0 = 1 only, P- eta = 0 (rank-6 column space: P+ has rank
+    2), and for unit links column (s, c) is P+[:, s] times the colour unit
+    vector e_c."""
+    L = (4, 4, 4, 6)
+    U = inputs.gauge_field(L, 0.3, seed=71, bc=SF)
+    eta = orc.sf_source(L, U)
+    mask = np.ones(6, bool)
+    mask[1] = False
+    assert np.all(eta[:, mask] == 0)
+    Pm = (np.eye(4) - GAM[3]) / 2
+    assert np.max(np.abs(np.einsum("ab,jtzyxbc->jtzyxac", Pm, eta))) < 1e-15
+    assert np.linalg.matrix_rank(eta[:, 1, 0, 0, 0].reshape(12, 12), tol=1e-12) == 6
+    e1 = orc.sf_source(L, inputs.unit_gauge(L))
+    Pp = (np.eye(4) + GAM[3]) / 2
+    for s in range(4):
+        for c in range(3):
+            col = np.zeros((4, 3), np.complex128)
+            col[:, c] = Pp[:, s]
+            assert np.allclose(e1[3 * s + c, 1], col)
+
+
+def _sf_fpfa(L, U, kappa=0.13, csw=1.5):
+    A = orc.clover_matrix(L, SF, U, orc.m0_from_kappa(kappa), csw)
+    th = (1, 1, 1, 1)
+    eta = orc.sf_source(L, U)
+    cols = []
+    for j in range(12):
+        x, rho, _, ok = orc.cg(L, SF, th, U, A, eta[j], tol=1e-12)
+        assert ok
+        cols.append(x)
+    H = np.stack(cols)
+    return H, orc.sf_correlators(L, H)
+
+
+def test_sf_correlators_gauge_invariant_and_from_meson_contraction():
+    """f_P and f_A are invariant under a random gauge transformation that is
+    1 on the boundary slice y0 = 0 (it fixes the boundary links): a source
+    built from U instead of U^+, or a missing P+, breaks this.  They equal
+    the meson contractions 1/2 C(g5, g5) and 1/2 C(Gamma_7, g5) (g5 g_t =
+    -Gamma_7), and f_P > 0 in the bulk."""
+    L = (4, 4, 4, 6)
+    U = inputs.gauge_field(L, 0.3, seed=72, bc=SF)
+    H, (fP, fA) = _sf_fpfa(L, U)
+    assert np.all(fP[1:].real > 0) and np.max(np.abs(fP.imag)) < 1e-14 and np.max(np.abs(fA.imag)) < 1e-13
+    rng = np.random.default_rng(73)
+    Om = haar_u3(rng, 6 * 64).reshape(6, 4, 4, 4, 3, 3)
+    Om[0] = np.eye(3)  # the boundary slice (y0 = 0, stored once for y0 = 0 and T)
+    Ug = gauge_transform(L, U, Om)
+    _, (fPg, fAg) = _sf_fpfa(L, Ug)
+    assert np.allclose(fPg, fP, rtol=1e-9) and np.allclose(fAg, fA, rtol=1e-9, atol=1e-12 * np.max(np.abs(fP)))
+    G = orc.meson_G(L, H)
+    assert np.allclose(fP, 0.5 * orc.meson_correlator(G, 15, 15), rtol=1e-12)
+    assert np.allclose(fA, 0.5 * orc.meson_correlator(G, 7, 15), rtol=1e-12, atol=1e-14)
+    assert np.allclose(orc.gamma(4) @ orc.gamma(3), -orc.gamma_product(7))
