@@ -27,6 +27,11 @@
  *   s_{mu nu} = (i/2)[g_mu, g_nu],   F = (1/8)(Q - Q^+) made traceless,
  *   Q = sum of the four plaquette leaves in the (mu,nu) plane around x.
  *
+ * Twisted mass: D(mu) = Dw + i mu g5 on every site, i.e. the site matrix
+ * A(x) + i mu g5 (the caller adds i mu g5 to A, see oracle.py); the adjoint
+ * uses g5 A^+ g5 for the site term (g5_adjoint_sites), so D(mu)^+ =
+ * g5 D(-mu) g5.
+ *
  * Chiral Euclidean gamma basis: g_t = [[0,-1],[-1,0]],
  * g_k = [[0,-i s_k],[i s_k,0]], g5 = g_t g_x g_y g_z = diag(1,1,-1,-1).
  *
@@ -396,11 +401,28 @@ void or_dw(const int *L, int bc, const double *th_re, const double *th_im,
   dw_apply(&g, U, A, psi, out);
 }
 
-/* Dw^+ = g5 Dw g5 */
-static void dwdag_apply(const lat_t *g, const cd *U, const cd *A, const cd *psi,
+/* Site matrices g5 A(x)^+ g5.  The hopping term H of Dw = A + H satisfies
+ * H^+ = g5 H g5, so Dw^+ = g5 (g5 A^+ g5 + H) g5: the adjoint is Dw with
+ * g5 A^+ g5 in place of A, between two g5.  For the clover term A is
+ * Hermitian and commutes with g5, so g5 A^+ g5 = A; a twisted mass
+ * i mu g5 in A turns into -i mu g5. */
+static cd *g5_adjoint_sites(const lat_t *g, const cd *A) {
+  cd *Ad = malloc((size_t)g->V * 144 * sizeof(cd));
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < g->V; ++x)
+    for (int r = 0; r < 12; ++r)
+      for (int c = 0; c < 12; ++c) {
+        const double sg = ((r < 6) == (c < 6)) ? 1.0 : -1.0;  /* g5_r g5_c */
+        Ad[x * 144 + r * 12 + c] = sg * conj(A[x * 144 + c * 12 + r]);
+      }
+  return Ad;
+}
+
+/* Dw^+ psi; Ad from g5_adjoint_sites */
+static void dwdag_apply(const lat_t *g, const cd *U, const cd *Ad, const cd *psi,
                         cd *out, cd *tmp) {
   g5_apply(g, psi, tmp);
-  dw_apply(g, U, A, tmp, out);
+  dw_apply(g, U, Ad, tmp, out);
   g5_apply(g, out, tmp);
   memcpy(out, tmp, (size_t)g->V * 12 * sizeof(cd));
 }
@@ -409,7 +431,9 @@ void or_dw_dag(const int *L, int bc, const double *th_re, const double *th_im,
                const cd *U, const cd *A, const cd *psi, cd *out) {
   lat_t g = make_lat(L, bc, th_re, th_im);
   cd *tmp = malloc((size_t)g.V * 12 * sizeof(cd));
-  dwdag_apply(&g, U, A, psi, out, tmp);
+  cd *Ad = g5_adjoint_sites(&g, A);
+  dwdag_apply(&g, U, Ad, psi, out, tmp);
+  free(Ad);
   free(tmp);
 }
 
@@ -451,9 +475,10 @@ int or_cg(const int *L, int bc, const double *th_re, const double *th_im,
   cd *r = malloc(n * sizeof(cd)), *p = malloc(n * sizeof(cd));
   cd *q = malloc(n * sizeof(cd)), *s = malloc(n * sizeof(cd));
   cd *tmp = malloc(n * sizeof(cd));
+  cd *Ad = g5_adjoint_sites(&g, A);
   for (long i = 0; i < n; ++i) psi[i] = 0;
 
-  dwdag_apply(&g, U, A, eta, r, tmp);       /* r = b = Dw^+ eta */
+  dwdag_apply(&g, U, Ad, eta, r, tmp);       /* r = b = Dw^+ eta */
   double bnorm = sqrt(norm2(n, r));
   double target = tol / 10.0;
   int it = 0, status = 1;
@@ -468,7 +493,7 @@ int or_cg(const int *L, int bc, const double *th_re, const double *th_im,
     dw_apply(&g, U, A, p, q);               /* q = Dw p */
     double pAp = norm2(n, q);               /* <p, Dw^+ Dw p> = |Dw p|^2 */
     double alpha = rr / pAp;
-    dwdag_apply(&g, U, A, q, s, tmp);       /* s = Dw^+ Dw p */
+    dwdag_apply(&g, U, Ad, q, s, tmp);       /* s = Dw^+ Dw p */
     for (long i = 0; i < n; ++i) {
       psi[i] += alpha * p[i];
       r[i] -= alpha * s[i];
@@ -481,7 +506,7 @@ int or_cg(const int *L, int bc, const double *th_re, const double *th_im,
       /* restart from the true residual */
       dw_apply(&g, U, A, psi, q);
       for (long i = 0; i < n; ++i) q[i] = eta[i] - q[i];
-      dwdag_apply(&g, U, A, q, r, tmp);
+      dwdag_apply(&g, U, Ad, q, r, tmp);
       target /= 10.0;
       memcpy(p, r, n * sizeof(cd));
       rr = norm2(n, r);
@@ -495,7 +520,7 @@ int or_cg(const int *L, int bc, const double *th_re, const double *th_im,
 done:
   if (rho_out) *rho_out = rho;
   if (iters_out) *iters_out = it;
-  free(r); free(p); free(q); free(s); free(tmp);
+  free(r); free(p); free(q); free(s); free(tmp); free(Ad);
   return status;
 }
 
@@ -509,15 +534,16 @@ double or_cg_fixed(const int *L, int bc, const double *th_re, const double *th_i
   cd *r = malloc(n * sizeof(cd)), *p = malloc(n * sizeof(cd));
   cd *q = malloc(n * sizeof(cd)), *s = malloc(n * sizeof(cd));
   cd *tmp = malloc(n * sizeof(cd));
+  cd *Ad = g5_adjoint_sites(&g, A);
   for (long i = 0; i < n; ++i) psi[i] = 0;
-  dwdag_apply(&g, U, A, eta, r, tmp);
+  dwdag_apply(&g, U, Ad, eta, r, tmp);
   double bb = norm2(n, r);
   memcpy(p, r, n * sizeof(cd));
   double rr = bb;
   for (int it = 0; it < niter && rr > 0.0; ++it) {
     dw_apply(&g, U, A, p, q);
     double alpha = rr / norm2(n, q);
-    dwdag_apply(&g, U, A, q, s, tmp);
+    dwdag_apply(&g, U, Ad, q, s, tmp);
     for (long i = 0; i < n; ++i) {
       psi[i] += alpha * p[i];
       r[i] -= alpha * s[i];
@@ -527,7 +553,7 @@ double or_cg_fixed(const int *L, int bc, const double *th_re, const double *th_i
     for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
     rr = rr_new;
   }
-  free(r); free(p); free(q); free(s); free(tmp);
+  free(r); free(p); free(q); free(s); free(tmp); free(Ad);
   return bb > 0.0 ? sqrt(rr / bb) : 0.0;
 }
 

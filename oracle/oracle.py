@@ -117,12 +117,18 @@ def field_strength(L, bc, U) -> np.ndarray:
     return F
 
 
-def clover_matrix(L, bc, U, m0, csw, cF=1.0) -> np.ndarray:
-    """Diagonal term A(x) as 12x12 matrices, A[t,z,y,x,12,12]."""
+def clover_matrix(L, bc, U, m0, csw, cF=1.0, mu=0.0) -> np.ndarray:
+    """Diagonal term A(x) as 12x12 matrices, A[t,z,y,x,12,12]; with a twisted
+    mass mu (paper Sec. 3.3, DiracParam's mu) the site term of
+    D(mu) = Dw + i mu g5, i.e. A(x) + i mu g5 (g5 = diag(1,1,-1,-1) on spin,
+    identity on colour)."""
     U = _c128(U)
     Lx, Ly, Lz, T = L
     A = np.zeros((T, Lz, Ly, Lx, 12, 12), np.complex128)
     _load().or_clover_matrix(_ptr(_Larr(L)), bc, _ptr(U), m0, csw, cF, _ptr(A))
+    if mu != 0.0:
+        g5 = np.diag(np.repeat(np.diag(gamma(4)), 3))
+        A = A + 1j * mu * g5
     return A
 
 
@@ -145,7 +151,8 @@ def dw(L, bc, theta, U, A, psi) -> np.ndarray:
 
 
 def dw_dag(L, bc, theta, U, A, psi) -> np.ndarray:
-    """Dw^+ psi = g5 Dw g5 psi."""
+    """Dw^+ psi: g5 Dw g5 psi with the site term replaced by g5 A^+ g5 (equal
+    to A for the clover term; i mu g5 becomes -i mu g5)."""
     U, A, psi = _c128(U), _c128(A), _c128(psi)
     out = np.zeros_like(psi)
     tr, ti = _theta(theta)

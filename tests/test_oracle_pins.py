@@ -570,3 +570,89 @@ def test_sf_correlators_gauge_invariant_and_from_meson_contraction():
     assert np.allclose(fP, 0.5 * orc.meson_correlator(G, 15, 15), rtol=1e-12)
     assert np.allclose(fA, 0.5 * orc.meson_correlator(G, 7, 15), rtol=1e-12, atol=1e-14)
     assert np.allclose(orc.gamma(4) @ orc.gamma(3), -orc.gamma_product(7))
+
+
+# ---- twisted mass (paper Sec. 3.3, DiracParam's mu): D(mu) = Dw + i mu g5 ----
+G5_12 = np.diag(np.repeat(np.diag(G5), 3))
+
+
+def test_twisted_mass_free_field_closed_form():
+    """U = 1 plane waves: D(mu) has the momentum-space form of Dw plus i mu g5."""
+    L = (4, 6, 4, 8)
+    Lx, Ly, Lz, T = L
+    rng = np.random.default_rng(5)
+    theta = np.exp(1j * np.array([0.3, -0.7, 0.0, np.pi]))
+    m0, mu = 0.137, 0.23
+    U = inputs.unit_gauge(L)
+    A = orc.clover_matrix(L, PERIODIC, U, m0, csw=1.7, mu=mu)
+    n = np.array([1, 2, 3, 1])
+    p = (2 * np.pi * n + np.angle(theta)) / np.array(L)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    out = orc.dw(L, PERIODIC, theta, U, A, phase[..., None, None] * u)
+    expect = phase[..., None, None] * ((free_dtilde(p, m0) + 1j * mu * G5) @ u)
+    assert rel(out, expect) < 1e-14
+
+
+@pytest.mark.parametrize("bc", [PERIODIC, SF, OPEN])
+def test_twisted_mass_norm_identity_and_adjoint(bc):
+    """|D(mu) psi|^2 = |Dw psi|^2 + mu^2 |psi|^2 (the cross term vanishes by
+    g5-hermiticity only for i mu g5: a missing i or g5 fails), and the
+    adjoint: <phi, D(mu)^+ chi> = <D(mu) phi, chi> with D(mu)^+ = g5 D(-mu) g5."""
+    L = (4, 4, 4, 6)
+    U, A0, theta = _setup(L, bc, seed=91, cF=1.2)
+    mu = 0.31
+    Ap = A0 + 1j * mu * G5_12
+    Am = A0 - 1j * mu * G5_12
+    psi = inputs.gaussian_spinor(L, 2, bc)
+    if bc == SF:
+        psi[0] = 0  # the Dirichlet slice is not part of the system
+    d0 = orc.dw(L, bc, theta, U, A0, psi)
+    d = orc.dw(L, bc, theta, U, Ap, psi)
+    n2 = lambda v: float(np.vdot(v, v).real)
+    assert abs(n2(d) - n2(d0) - mu ** 2 * n2(psi)) < 1e-12 * n2(d)
+    phi, chi = inputs.gaussian_spinor(L, 3, bc), inputs.gaussian_spinor(L, 4, bc)
+    if bc == SF:
+        phi[0] = chi[0] = 0
+    lhs = np.vdot(phi, orc.dw_dag(L, bc, theta, U, Ap, chi))
+    rhs = np.vdot(orc.dw(L, bc, theta, U, Ap, phi), chi)
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+    g5 = lambda v: np.concatenate([v[..., :2, :], -v[..., 2:, :]], axis=-2)
+    assert rel(orc.dw_dag(L, bc, theta, U, Ap, chi), g5(orc.dw(L, bc, theta, U, Am, g5(chi)))) < 1e-14
+
+
+@pytest.mark.parametrize("L,bc", [((2, 2, 2, 2), PERIODIC), ((2, 2, 2, 4), SF), ((2, 2, 2, 4), OPEN)])
+def test_twisted_mass_cg_and_schur_against_dense_solve(L, bc):
+    """CG (normal equations with the true adjoint) and the even-odd Schur
+    route with non-Hermitian blocks A +- i mu both reproduce the dense solve."""
+    U, A0, theta = _setup(L, bc, seed=92, eps=0.3, cF=1.1, m0=0.1667)
+    A = A0 + 1j * 0.27 * G5_12
+    x0 = (0, 0, 0, 1) if bc == SF else (0, 0, 0, 0)
+    eta = inputs.point_source(L, x0, 1, 2) + 0.5 * inputs.gaussian_spinor(L, 4, bc)
+    psi, rho, iters, ok = orc.cg(L, bc, theta, U, A, eta, tol=1e-13)
+    assert ok and rho <= 1e-13
+    M = orc.dense_dw(L, bc, theta, U, A)
+    shape = L[::-1] + (4, 3)
+    act = np.ones(shape, bool)
+    if bc == SF:
+        act[0] = False
+    idx = np.flatnonzero(act.reshape(-1))
+    ref = np.zeros(M.shape[0], complex)
+    ref[idx] = np.linalg.solve(M[np.ix_(idx, idx)], eta.reshape(-1)[idx])
+    assert rel(psi.reshape(-1), ref) < 1e-11
+    Ainv = orc.inverse_blocks(A)
+    even = (~orc.parity_mask(L))[..., None, None] & act
+    eidx = np.flatnonzero(even.reshape(-1))
+    n = M.shape[0]
+    Dh = np.zeros((n, len(eidx)), complex)
+    e = np.zeros(shape, complex)
+    for j, k in enumerate(eidx):
+        e.reshape(-1)[k] = 1
+        Dh[:, j] = orc.schur_dhat(L, bc, theta, U, A, Ainv, e).reshape(-1)
+        e.reshape(-1)[k] = 0
+    eh = orc.schur_source(L, bc, theta, U, Ainv, eta).reshape(-1)
+    xe = np.zeros(n, complex)
+    xe[eidx] = np.linalg.solve(Dh[eidx], eh[eidx])
+    full = orc.schur_reconstruct(L, bc, theta, U, Ainv, eta, xe.reshape(shape))
+    assert rel(full.reshape(-1), ref) < 1e-12
