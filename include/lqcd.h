@@ -16,6 +16,9 @@
  *                                        + ph- (1+g_mu) U_mu(x-mu)^+ psi(x-mu) ]
  *   A(x) = (4 + m0 + d_bnd(x)(cF-1)) + csw (i/4) sum_{mu!=nu} s_{mu nu} F_{mu nu}(x),
  *   m0 = 1/(2 kappa) - 4, F the traceless clover-leaf field strength.
+ * With a twisted mass mu the operator is D(mu) = Dw + i mu g5 on every site
+ * (its adjoint is g5 D(-mu) g5); every call below that takes lqcd_dirac
+ * applies or inverts D(mu) (Dw for mu = 0).
  * Boundary handling: PERIODIC multiplies hops crossing the edge of direction
  * mu by theta_mu (conj(theta_mu) backwards); SF makes slice t = 0 a
  * Dirichlet slice (output 0 there, input there ignored, d_bnd = 1 on
@@ -139,13 +142,15 @@ typedef struct lqcd_dirac {
   double kappa;  /* hopping parameter > 0; m0 = 1/(2 kappa) - 4 */
   double csw;    /* Sheikholeslami-Wohlert coefficient */
   double cF;     /* boundary coefficient (c~_t) for SF/OPEN; 1 = tree level */
-  double mu;     /* twisted mass: must be 0 in this build (EUNSUPPORTED) */
+  double mu;     /* twisted mass: D(mu) = Dw + i mu g5 (0: plain Dw) */
 } lqcd_dirac;
 
 /* Csw! analogue (paper Sec. 3.3): computes the clover term of (u, d) into
  * the workspace, in FP64 and in the other precisions the workspace holds:
  * A(x) on every site and A(x)^{-1} on the odd sites (FP64 6x6 LDL^H per
- * chirality block).  ENUMERIC if a block is numerically singular.  Later
+ * chirality block); with mu != 0 the odd sites hold (A + i mu g5)^{-1} per
+ * chirality, (A^2 + mu^2)^{-1}(A -+ i mu), as general 6x6 blocks.  ENUMERIC
+ * if a block is numerically singular.  Later
  * calls with the same (u, d) reuse it; lqcd_dw_apply and lqcd_solve call
  * this themselves when needed. */
 int lqcd_clover(const lqcd_gauge_t *u, const lqcd_dirac *d, lqcd_ws_t *w, void *stream);
@@ -153,11 +158,11 @@ int lqcd_clover(const lqcd_gauge_t *u, const lqcd_dirac *d, lqcd_ws_t *w, void *
 /* ---- operator application (paper Sec. 3.3: Dw!, g5Dw!, DwdagDw!) ------- */
 enum {
   LQCD_OP_DW = 0,          /* full-lattice Dw */
-  LQCD_OP_DW_DAG = 1,      /* Dw^+ = g5 Dw g5 */
+  LQCD_OP_DW_DAG = 1,      /* D^+ = g5 D(-mu) g5 */
   LQCD_OP_G5DW = 2,        /* g5 Dw */
-  LQCD_OP_DWDAGDW = 3,     /* Dw^+ Dw */
+  LQCD_OP_DWDAGDW = 3,     /* D^+ D */
   LQCD_OP_SCHUR = 4,       /* Dhat = A_ee - D_eo A_oo^{-1} D_oe on even sites */
-  LQCD_OP_SCHUR_DAG = 5,   /* Dhat^+ = g5 Dhat g5 */
+  LQCD_OP_SCHUR_DAG = 5,   /* Dhat^+ = g5 Dhat(-mu) g5 */
   LQCD_OP_SCHUR_NORMAL = 6,/* Dhat^+ Dhat */
   LQCD_OP_HOP_EO = 7,      /* A_oo^{-1} D_oe: even input -> odd output */
   LQCD_OP_HOP_OE = 8       /* A_ee x_e - D_eo y_o: see lqcd_dw_apply */

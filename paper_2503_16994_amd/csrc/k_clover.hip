@@ -271,12 +271,32 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
     store_packed(c.C64 + par, s, 18 * b, B);
     if (c.C32) store_packed(c.C32 + par, s, 18 * b, B);
     if (c.C16) store_packed(c.C16 + par, s, 18 * b, B);
-    if (p == 1) {
+    if (p == 1 && c.mu == 0.0) {
       cd R[6][6];
       if (!herm6_inverse(B, R)) atomicOr(c.err_flag, 1);
       store_packed(c.Ci64, s, 18 * b, R);
       if (c.Ci32) store_packed(c.Ci32, s, 18 * b, R);
       if (c.Ci16) store_packed(c.Ci16, s, 18 * b, R);
+    } else if (p == 1) {
+      // twisted mass: the block of chirality b is B + i sg mu (g5 = sg on
+      // it).  B is Hermitian, so (B + i m)^{-1} = (B^2 + mu^2)^{-1} (B - i m)
+      // for m = +-mu (and the adjoint is the same with -m): the odd sites
+      // store the Hermitian positive definite Q^{-1} = (B^2 + mu^2)^{-1}
+      // (LDL^H), the hop kernels apply B and the i m term themselves
+      cd Q[6][6], Qi[6][6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          cd v = {i == j ? c.mu * c.mu : 0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 6; ++k) v = cadd(v, cmul(B[i][k], B[k][j]));
+          Q[i][j] = v;
+        }
+      if (!herm6_inverse(Q, Qi)) atomicOr(c.err_flag, 1);
+      store_packed(c.Ci64, s, 18 * b, Qi);
+      if (c.Ci32) store_packed(c.Ci32, s, 18 * b, Qi);
+      if (c.Ci16) store_packed(c.Ci16, s, 18 * b, Qi);
     }
   }
 }

@@ -91,6 +91,13 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
   }
 }
 
+// out6 += i m in6 (m = +-mu: the twisted-mass term of one chirality block)
+template <typename A>
+__device__ inline void add_tm(A m, const cpx<A> (&in6)[6], cpx<A> (&o6)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) o6[i] = {o6[i].re - m * in6[i].im, o6[i].im + m * in6[i].re};
+}
+
 template <typename A, typename SG>
 __device__ inline void load_block(const SG* C, int blk, int s, bool cached, cpx<A> (&m)[18]) {
   const SG* c = C + tix(s, 36) + blk * 18 * kTile;
@@ -200,9 +207,10 @@ struct ThreadSite {
 // the dependent loads each: for lattices too small to fill the GPU.  The hop
 // sum is (x, y terms) + (z, t terms) instead of one chain over the eight, so
 // results differ from the unsplit kernel in the last bits.
-template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT, typename A>
+template <typename SG, typename SI, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT, bool TM, typename A>
 __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v)[NR][12], cpx<A>* xch) {
   static_assert(!SPLIT || (NR == 1 && RL == 1 && HOP), "direction split: one rhs per thread");
+  static_assert(!TM || (NR == 1 && RL == 1), "twisted mass: one rhs per thread");
   constexpr int SPB = SPLIT ? 64 : kHopBlock / RL;  // sites per block
   // wave index (uniform over the wave; only the split uses it)
   const int wv = SPLIT ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
@@ -307,15 +315,23 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
       } else {
         cpx<A> o6[6];
         herm6_mul(Cm, in6, o6);
+        if constexpr (TM) add_tm((A)(wv == 0 ? a.tm_mu : -a.tm_mu), in6, o6);
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[0][i] = cadd(v[0][i], o6[i]);
       }
     }
     if (ts.active && POST == POST_CLOV) {
-      cpx<A> Ci[18], in6[6], o6[6];
-      load_block(static_cast<const SG*>(a.Cpost), wv, s, a.cached_gauge != 0, Ci);
+      cpx<A> in6[6], o6[6], Ci[18];
 #pragma unroll
       for (int i = 0; i < 6; ++i) in6[i] = v[0][i];
+      if constexpr (TM) {  // (A + i m)^{-1} = Q^{-1} (A - i m), m = tm_mu g5
+        load_block(static_cast<const SG*>(a.Ctm), wv, s, a.cached_gauge != 0, Ci);
+        herm6_mul(Ci, in6, o6);
+        add_tm((A)(wv == 0 ? -a.tm_mu : a.tm_mu), in6, o6);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) in6[i] = o6[i];
+      }
+      load_block(static_cast<const SG*>(a.Cpost), wv, s, a.cached_gauge != 0, Ci);
       herm6_mul(Ci, in6, o6);
 #pragma unroll
       for (int i = 0; i < 6; ++i) v[0][i] = o6[i];
@@ -355,13 +371,44 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
         } else {
           cpx<A> o6[6];
           herm6_mul(Cm, in6, o6);
+          if constexpr (TM) add_tm((A)(b == 0 ? a.tm_mu : -a.tm_mu), in6, o6);
 #pragma unroll
           for (int i = 0; i < 6; ++i) v[r][6 * b + i] = cadd(v[r][6 * b + i], o6[i]);
         }
       }
     }
   }
-  if (ts.active && POST == POST_CLOV) {
+  if (TM && ts.active && POST == POST_CLOV) {
+    // twisted mass: (A + i m)^{-1} = Q^{-1} (A - i m) per chirality
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      {
+        cpx<A> Cm[18];
+        load_block(static_cast<const SG*>(a.Ctm), b, s, a.cached_gauge != 0, Cm);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          cpx<A> in6[6], o6[6];
+#pragma unroll
+          for (int i = 0; i < 6; ++i) in6[i] = v[r][6 * b + i];
+          herm6_mul(Cm, in6, o6);
+          add_tm((A)(b == 0 ? -a.tm_mu : a.tm_mu), in6, o6);
+#pragma unroll
+          for (int i = 0; i < 6; ++i) v[r][6 * b + i] = o6[i];
+        }
+      }
+      cpx<A> Ci[18];
+      load_block(static_cast<const SG*>(a.Cpost), b, s, a.cached_gauge != 0, Ci);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        cpx<A> in6[6], o6[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) in6[i] = v[r][6 * b + i];
+        herm6_mul(Ci, in6, o6);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[r][6 * b + i] = o6[i];
+      }
+    }
+  } else if (ts.active && POST == POST_CLOV) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       cpx<A> Ci[18];
@@ -417,7 +464,7 @@ __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
   __syncthreads();
 }
 
-template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT>
+template <typename SG, typename SI, typename SO, int PRE, int POST, bool HOP, int NR, int RL, bool SPLIT, bool TM>
 __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
   constexpr int NC = SPLIT ? 6 : 12;  // output components per thread
@@ -426,7 +473,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
   if (a.alpha_cg) fused_alpha(a, red);
   ThreadSite ts;
   cpx<A> v[NR][12];
-  if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL, SPLIT>(a, ts, v, xch)) return;
+  if (!hop_thread<SG, SI, PRE, POST, HOP, NR, RL, SPLIT, TM>(a, ts, v, xch)) return;
   SO* ob = static_cast<SO*>(a.out);
   if (a.both) ob += ts.p * a.par_stride;
   // padding sites of the last tile (inactive, v = 0) are written too, so
@@ -462,7 +509,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
 // Ap = g5 (A_ee q + 1/2 H t) computed in registers, every rhs that is not done
 // gets x += alpha p, r -= alpha Ap (x, r, p of type SV at this site) and the
 // per-block |r|^2 partial.  Ap is never stored.
-template <typename SG, typename SI, typename SV, int NR, int RL, bool SPLIT>
+template <typename SG, typename SI, typename SV, int NR, int RL, bool SPLIT, bool TM>
 __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
   using AV = typename StoreTraits<SV>::acc;
@@ -471,7 +518,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   __shared__ cpx<A> xch[SPLIT ? 2 * 6 * 64 : 1];
   ThreadSite ts;
   cpx<A> v[NR][12];
-  if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL, SPLIT>(a, ts, v, xch)) return;
+  if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL, SPLIT, TM>(a, ts, v, xch)) return;
   SV* xb = static_cast<SV*>(a.xr_x);
   SV* rb = static_cast<SV*>(a.xr_r);
   const SV* pb = static_cast<const SV*>(a.xr_p);
@@ -510,6 +557,9 @@ static int sites_per_block(int rl, bool split = false) {
 }
 // the direction split applies to launches with one rhs per thread only
 static bool split_on(const HopLaunch& h) { return h.dir_split && h.nr_tile == 1 && h.rhs_lanes == 1; }
+// twisted-mass kernels exist for one rhs per thread (the launch helpers of
+// the library set nr_tile = rhs_lanes = 1 whenever mu != 0)
+static bool tm_on(const HopLaunch& h) { return h.tm_post != 0 || h.tm_mu != 0.0; }
 
 // Unused dynamic LDS that caps the workgroups resident per CU (160 KiB of LDS
 // per CU, plus each workgroup's small static reduction array): level 1 -> 4,
@@ -569,15 +619,29 @@ static hipError_t launch_rl(const HopLaunch& h, hipStream_t st) {
   switch (h.nr_tile) {
     case 1:
       if constexpr (RL == 1) {
+        if (tm_on(h)) {
+          if (split_on(h))
+            k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, true, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          else
+            k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, false, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          break;
+        }
         if (split_on(h)) {
-          k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, true, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
           break;
         }
       }
-      k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop<SG, SI, SO, PRE, POST, HOP, 1, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
       break;
-    case 2: k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 3: k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 2:
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop<SG, SI, SO, PRE, POST, HOP, 2, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
+    case 3:
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop<SG, SI, SO, PRE, POST, HOP, 3, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -607,15 +671,29 @@ static hipError_t launch_xr_rl(const HopLaunch& h, hipStream_t st) {
   switch (h.nr_tile) {
     case 1:
       if constexpr (RL == 1) {
+        if (tm_on(h)) {
+          if (split_on(h))
+            k_hop_xr<SG, SI, SV, 1, 1, true, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          else
+            k_hop_xr<SG, SI, SV, 1, 1, false, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          break;
+        }
         if (split_on(h)) {
-          k_hop_xr<SG, SI, SV, 1, 1, true><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+          k_hop_xr<SG, SI, SV, 1, 1, true, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
           break;
         }
       }
-      k_hop_xr<SG, SI, SV, 1, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop_xr<SG, SI, SV, 1, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
       break;
-    case 2: k_hop_xr<SG, SI, SV, 2, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
-    case 3: k_hop_xr<SG, SI, SV, 3, RL, false><<<grid, kHopBlock, h.lds_cap, st>>>(h); break;
+    case 2:
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop_xr<SG, SI, SV, 2, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
+    case 3:
+      if (tm_on(h)) return hipErrorInvalidValue;
+      k_hop_xr<SG, SI, SV, 3, RL, false, false><<<grid, kHopBlock, h.lds_cap, st>>>(h);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -660,7 +738,10 @@ static hipError_t launch_single(const HopLaunch& h0, hipStream_t st) {
   h.dir_split = 0;
   if (!prepare(h)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)h.nbs * (unsigned)h.nrhs;
-  k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, false><<<grid, kHopBlock, 0, st>>>(h);
+  if (tm_on(h))
+    k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, false, true><<<grid, kHopBlock, 0, st>>>(h);
+  else
+    k_hop<SG, SI, SO, PRE, POST, HOP, 1, 1, false, false><<<grid, kHopBlock, 0, st>>>(h);
   return hipGetLastError();
 }
 

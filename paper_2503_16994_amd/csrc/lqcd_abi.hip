@@ -295,7 +295,7 @@ int check_dirac(const lqcd_dirac* d) {
   if (!d) return fail(LQCD_EINVAL, "null Dirac parameters");
   if (!(d->kappa > 0.0) || !isfinite(d->kappa)) return fail(LQCD_EINVAL, "kappa must be > 0");
   if (!isfinite(d->csw) || !isfinite(d->cF)) return fail(LQCD_EINVAL, "csw and cF must be finite");
-  if (d->mu != 0.0) return fail(LQCD_EUNSUPPORTED, "twisted mass mu != 0 is not implemented");
+  if (!isfinite(d->mu)) return fail(LQCD_EINVAL, "mu must be finite");
   return LQCD_OK;
 }
 
@@ -306,7 +306,7 @@ int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipS
     return fail(LQCD_EINVAL, "gauge field and workspace have different geometries");
   const int want = w->pmask & u->pmask;
   if (w->clover_valid && w->clover_uid == u->uid && w->kappa == d->kappa && w->csw == d->csw &&
-      w->cF == d->cF && (w->clover_pmask & want) == want)
+      w->cF == d->cF && w->mu == d->mu && (w->clover_pmask & want) == want)
     return LQCD_OK;
   CloverLaunch c;
   c.g = w->g->kg;
@@ -315,6 +315,7 @@ int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipS
   c.m0 = 1.0 / (2.0 * d->kappa) - 4.0;
   c.csw = d->csw;
   c.cF = d->cF;
+  c.mu = d->mu;
   c.C64 = w->m.C64;
   c.Ci64 = w->m.Ci64;
   c.C32 = (want & LQCD_PM_F32) ? w->m.C32 : nullptr;
@@ -334,6 +335,7 @@ int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipS
   w->kappa = d->kappa;
   w->csw = d->csw;
   w->cF = d->cF;
+  w->mu = d->mu;
   w->clover_pmask = want | LQCD_PM_F64;
   return LQCD_OK;
 }
@@ -356,6 +358,7 @@ struct OpCtx {
   int prec;
   int nrhs;
   hipStream_t st;
+  double mu;  // twisted mass
 };
 
 static const void* links_of(const lqcd_gauge* u, int prec) {
@@ -368,7 +371,9 @@ static const void* cloi_of(const lqcd_ws* w, int prec) {
   return prec == P_F64 ? (const void*)w->m.Ci64 : (prec == P_F32 ? (const void*)w->m.Ci32 : (const void*)w->m.Ci16);
 }
 
-static HopLaunch base_launch(const OpCtx& c) {
+// dag: the launch belongs to the adjoint operator g5 D(-mu) g5 (twisted
+// mass -mu, adjoint odd-site inverse); no difference for mu = 0
+static HopLaunch base_launch(const OpCtx& c, bool dag) {
   HopLaunch h;
   memset(&h, 0, sizeof(h));
   h.g = c.w->g->kg;
@@ -377,7 +382,10 @@ static HopLaunch base_launch(const OpCtx& c) {
   h.two_row = c.u->two_row;
   h.nrhs = c.nrhs;
   h.hop = true;
+  h.tm_mu = dag ? -c.mu : c.mu;
+  h.tm_post = c.mu != 0.0 ? 1 : 0;
   apply_tuning(h, c.w->tune[c.prec]);
+  if (c.mu != 0.0) single_tile(h);  // twisted-mass kernels: one rhs per thread
   return h;
 }
 
@@ -390,9 +398,10 @@ static char* elem_ptr(void* base, int prec, long elems) {
 }
 
 // out (full) = Dw y on both parities, optional g5 on the output and partials
-static hipError_t apply_dw_full(const OpCtx& c, const void* y, void* out, bool g5, double* partials) {
+static hipError_t apply_dw_full(const OpCtx& c, const void* y, void* out, bool g5, double* partials,
+                                bool dag = false) {
   const lqcd_geom_t* g = c.w->g;
-  HopLaunch h = base_launch(c);
+  HopLaunch h = base_launch(c, dag);
   h.both = true;
   h.par_stride = par_off(g);
   h.cpre_par = 36L * g->V2p;
@@ -410,14 +419,15 @@ static hipError_t apply_dw_full(const OpCtx& c, const void* y, void* out, bool g
 }
 
 // t_o = A_oo^{-1} D_oe y_e (tmp odd part of `t` full vector)
-static hipError_t apply_hop_eo(const OpCtx& c, const void* y_full, void* t_full) {
+static hipError_t apply_hop_eo(const OpCtx& c, const void* y_full, void* t_full, bool dag = false) {
   const lqcd_geom_t* g = c.w->g;
-  HopLaunch h = base_launch(c);
+  HopLaunch h = base_launch(c, dag);
   h.p_out = 1;
   h.y = y_full;
   h.out = elem_ptr(t_full, c.prec, par_off(g));
   h.y_rs = h.out_rs = full_rs(g);
   h.Cpost = cloi_of(c.w, c.prec);
+  h.Ctm = elem_ptr((void*)clov_of(c.w, c.prec), c.prec, 36L * g->V2p);  // A on the odd sites
   h.pre = PRE_NONE;
   h.post = POST_CLOV;
   h.scale = -0.5;
@@ -426,9 +436,9 @@ static hipError_t apply_hop_eo(const OpCtx& c, const void* y_full, void* t_full)
 
 // out_e = A_ee z_e + 1/2 H t_o  (= Dhat z when t = A_oo^{-1} D_oe z)
 static hipError_t apply_hop_oe(const OpCtx& c, const void* z_full, const void* t_full, void* out_full,
-                               bool g5, double* partials) {
+                               bool g5, double* partials, bool dag = false) {
   const lqcd_geom_t* g = c.w->g;
-  HopLaunch h = base_launch(c);
+  HopLaunch h = base_launch(c, dag);
   h.p_out = 0;
   h.y = elem_ptr((void*)t_full, c.prec, par_off(g));
   h.z = z_full;
@@ -462,7 +472,7 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
   if (rc) return rc;
 
   const lqcd_geom_t* g = w->g;
-  OpCtx c{u, w, prec, nrhs, st};
+  OpCtx c{u, w, prec, nrhs, st, d->mu};
   // internal-layout operands: caller's memory or workspace FP64 slots reused
   // as storage of any precision (they are the widest)
   const void* vin = in;
@@ -488,11 +498,11 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
         LQCD_HIP(launch_g5(tmp2, prec, g->V2p, 12L * g->V2p, 2 * nrhs, st));
         vin = tmp2;
       }
-      LQCD_HIP(apply_dw_full(c, vin, vout, true, nullptr));
+      LQCD_HIP(apply_dw_full(c, vin, vout, true, nullptr, true));
       break;
-    case LQCD_OP_DWDAGDW:
+    case LQCD_OP_DWDAGDW:  // g5 D(-mu) g5 D(mu)
       LQCD_HIP(apply_dw_full(c, vin, tmp, true, nullptr));
-      LQCD_HIP(apply_dw_full(c, tmp, vout, true, nullptr));
+      LQCD_HIP(apply_dw_full(c, tmp, vout, true, nullptr, true));
       break;
     case LQCD_OP_SCHUR:
     case LQCD_OP_SCHUR_DAG:
@@ -502,15 +512,18 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
         vin = tmp2;
       }
       if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
-      LQCD_HIP(apply_hop_eo(c, vin, tmp));
-      LQCD_HIP(apply_hop_oe(c, vin, tmp, vout, op == LQCD_OP_SCHUR_DAG, nullptr));
+      {
+        const bool dag = (op == LQCD_OP_SCHUR_DAG);  // g5 Dhat(-mu) g5
+        LQCD_HIP(apply_hop_eo(c, vin, tmp, dag));
+        LQCD_HIP(apply_hop_oe(c, vin, tmp, vout, dag, nullptr, dag));
+      }
       break;
-    case LQCD_OP_SCHUR_NORMAL:
+    case LQCD_OP_SCHUR_NORMAL:  // g5 Dhat(-mu) g5 Dhat(mu)
       if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
       LQCD_HIP(apply_hop_eo(c, vin, tmp));
       LQCD_HIP(apply_hop_oe(c, vin, tmp, tmp2, true, nullptr));
-      LQCD_HIP(apply_hop_eo(c, tmp2, tmp));
-      LQCD_HIP(apply_hop_oe(c, tmp2, tmp, vout, true, nullptr));
+      LQCD_HIP(apply_hop_eo(c, tmp2, tmp, true));
+      LQCD_HIP(apply_hop_oe(c, tmp2, tmp, vout, true, nullptr, true));
       break;
     case LQCD_OP_HOP_EO:
       if (canon) LQCD_HIP(launch_fill_zero(vout, full_bytes, st));
@@ -629,7 +642,7 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   const int keep = saved.flags & LQCD_TUNE_DIR_SPLIT;  // the caller's choice
   double best_t = 1e300;
   lqcd_tuning best_cfg = saved;
-  OpCtx c{u, w, prec, nrhs, st};
+  OpCtx c{u, w, prec, nrhs, st, d->mu};
   hipError_t err = hipSuccess;
   // times the workspace's current tuning; keeps it if it is the fastest so far
   auto trial = [&]() {

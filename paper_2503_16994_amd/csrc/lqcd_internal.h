@@ -59,6 +59,7 @@ struct WsLayout {
 struct GraphEntry {
   uint64_t gauge_uid;
   int solver, inner_prec, nrhs, chunk;
+  double mu;  // twisted mass (a kernel argument of the captured launches)
   lqcd_tuning tune_inner, tune_f64;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -77,7 +78,7 @@ struct lqcd_ws {
   // clover cache key
   bool clover_valid = false;
   uint64_t clover_uid = 0;
-  double kappa = 0, csw = 0, cF = 0;
+  double kappa = 0, csw = 0, cF = 0, mu = 0;
   int clover_pmask = 0;
   std::vector<GraphEntry> graphs;
   lqcd_tuning tune[3] = {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}};  // nr, order, lanes, flags

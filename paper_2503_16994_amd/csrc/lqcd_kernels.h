@@ -62,6 +62,13 @@ struct HopLaunch {
   int occ_cap;       // 0..3: cap on resident workgroups per CU (unused LDS)
   int dir_split;     // 1: two waves per site block split the hop directions
                      // (launches with nr_tile = rhs_lanes = 1 only)
+  // twisted mass tm_mu (+-mu: -mu in launches of the adjoint operator,
+  // since D(mu)^+ = g5 D(-mu) g5): PRE_CLOV adds i tm_mu g5 z; with tm_post
+  // POST_CLOV applies (A + i tm_mu g5)^{-1} = Q^{-1} (A - i tm_mu g5) per
+  // chirality, with Q^{-1} = (A^2 + mu^2)^{-1} in Cpost and A in Ctm
+  double tm_mu;
+  int tm_post;
+  const void* Ctm;  // clover blocks A of the output parity (tm_post only)
   unsigned lds_cap;  // dynamic LDS bytes of the launch (set by the launcher)
   // filled in by the launcher
   int nbs;  // site blocks (both parities in `both` mode)
@@ -123,6 +130,7 @@ struct CloverLaunch {
   const double2* U64;
   int two_row;  // links stored as their first two rows (6 complex)
   double m0, csw, cF;
+  double mu;    // twisted mass: odd sites hold (A^2 + mu^2)^{-1} instead of A^{-1}
   double2* C64;     // two parities, each a tiled 36-component field
   double2* Ci64;    // tiled 36-component field: inverse on the odd sites
   float2* C32;

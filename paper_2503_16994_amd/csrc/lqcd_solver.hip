@@ -48,7 +48,16 @@ struct Ctl {
   const lqcd_gauge* u;
   lqcd_ws* w;
   int nrhs;
+  double mu;         // twisted mass
+  bool dag = false;  // launches of the adjoint operator g5 D(-mu) g5
 };
+
+// the same context for the adjoint operator (D(mu)^+ = g5 D(-mu) g5)
+Ctl dg(const Ctl& c) {
+  Ctl d = c;
+  d.dag = true;
+  return d;
+}
 
 const void* links_of(const lqcd_gauge* u, int prec) {
   return prec == P_F64 ? (const void*)u->U64 : (prec == P_F32 ? (const void*)u->U32 : (const void*)u->U16);
@@ -81,7 +90,10 @@ HopLaunch mk(const Ctl& c, int lprec) {
   h.two_row = c.u->two_row;
   h.nrhs = c.nrhs;
   h.hop = true;
+  h.tm_mu = c.dag ? -c.mu : c.mu;
+  h.tm_post = c.mu != 0.0 ? 1 : 0;
   apply_tuning(h, c.w->tune[lprec]);
+  if (c.mu != 0.0) single_tile(h);  // twisted-mass kernels: one rhs per thread
   return h;
 }
 
@@ -101,6 +113,7 @@ hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, in
   h.out = out_o.p;
   h.out_rs = out_o.rs;
   h.Cpost = cloi_of(c.w, lprec);
+  h.Ctm = (const char*)clov_of(c.w, lprec) + (size_t)36 * c.g->V2p * elem_bytes(lprec);  // A, odd sites
   h.pre = PRE_NONE;
   h.post = POST_CLOV;
   h.scale = -0.5;
@@ -218,6 +231,7 @@ hipError_t clover_inv_apply(const Ctl& c, Vec z_o, Vec y_e, Vec out_o, bool hop,
   h.out = out_o.p;
   h.out_rs = out_o.rs;
   h.Cpost = c.w->m.Ci64;
+  h.Ctm = c.w->m.C64 + (size_t)36 * c.g->V2p;  // A on the odd sites
   h.pre = PRE_IDENT;
   h.post = POST_CLOV;
   h.hop = hop;
@@ -254,7 +268,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   const lqcd_geom_t* g = w->g;
   const long V2 = g->V2p;  // field rows per parity (sites incl. padding)
   const WsLayout& m = w->m;
-  Ctl c{st, g, u, w, N};
+  Ctl c{st, g, u, w, N, prm->d.mu};
   const long FRS = 24 * V2, HRS = 12 * V2;
   const bool eo = (prm->solver == LQCD_SOLVER_CG_EO);
   const bool mixed = eo && ip != LQCD_F64;
@@ -311,12 +325,12 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     LQCD_HIP(hop_oe_ident(c, E, odd_part(TMP, V2), EH));                               // eta_hat
     LQCD_HIP(hipMemcpyAsync(m.AP, m.EH, full_bytes, hipMemcpyDeviceToDevice, st));
     LQCD_HIP(launch_g5(m.AP, P_F64, V2, FRS, N, st));
-    LQCD_HIP(hop_eo(c, P_F64, AP, odd_part(TMP, V2), nullptr, 1));
-    LQCD_HIP(hop_oe(c, P_F64, AP, odd_part(TMP, V2), R, true, parts, nullptr, 1));
+    LQCD_HIP(hop_eo(dg(c), P_F64, AP, odd_part(TMP, V2), nullptr, 1));
+    LQCD_HIP(hop_oe(dg(c), P_F64, AP, odd_part(TMP, V2), R, true, parts, nullptr, 1));
     nb_op = nb_hop;
   } else {
     LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.Q, P_F64, N, true, st));  // g5 eta
-    LQCD_HIP(dw_full(c, m.Q, m.R, true, parts, nullptr));
+    LQCD_HIP(dw_full(dg(c), m.Q, m.R, true, parts, nullptr));
     nb_op = 2 * nb_hop;
   }
   LQCD_HIP(launch_reduce(parts, nb_op, N, scal, st));
@@ -373,14 +387,14 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, 1))) return e;
       if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, 1))) return e;
       if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, N, cg, parts2, st))) return e;
-      if ((e = hop_eo(c, P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
-      if ((e = hop_oe(c, P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, 1))) return e;
+      if ((e = hop_eo(dg(c), P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
+      if ((e = hop_oe(dg(c), P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, 1))) return e;
       if (lo && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
       return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_hop, N, st);
     }
     if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
     if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, N, cg, parts2, st))) return e;
-    if ((e = dw_full(c, m.AP, m.R, true, parts, skip_ru))) return e;
+    if ((e = dw_full(dg(c), m.AP, m.R, true, parts, skip_ru))) return e;
     return launch_ru_finish(cg, parts2, blas_nblocks(24 * V2), parts, 2 * nb_hop, N, st);
   };
 
@@ -396,13 +410,13 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       const int nb_it = iter_parts(c, lprec);
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
-      if ((e = hop_eo(c, lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
-      if ((e = hop_oe_xr(c, lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
+      if ((e = hop_eo(dg(c), lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
+      if ((e = hop_oe_xr(dg(c), lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
       nb_r = nb_it;
     } else {
       if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
       if ((e = launch_cg_alpha(cg, parts, nb_op, N, st))) return e;
-      if ((e = dw_full(c, (const double2*)qin.p, (double2*)api.p, true, nullptr, done))) return e;
+      if ((e = dw_full(dg(c), (const double2*)qin.p, (double2*)api.p, true, nullptr, done))) return e;
       if ((e = launch_cg_xr(xi.p, xi.prec, xi.rs, ri.p, pi.p, api.p, ri.prec, n_vec, ri.rs, N, cg, parts,
                             st)))
         return e;
@@ -426,7 +440,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       hipGraphExec_t exec = nullptr;
       for (auto& e : w->graphs)
         if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == key_prec && e.nrhs == N &&
-            e.chunk == K && same_tuning(e.tune_inner, w->tune[key_prec]) && same_tuning(e.tune_f64, w->tune[P_F64]))
+            e.chunk == K && e.mu == c.mu && same_tuning(e.tune_inner, w->tune[key_prec]) &&
+            same_tuning(e.tune_f64, w->tune[P_F64]))
           exec = e.exec;
       if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -444,7 +459,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
           (void)hipGraphDestroy(gr);
           return hip_status(e3, "hipGraphInstantiate");
         }
-        w->graphs.push_back(GraphEntry{u->uid, prm->solver, key_prec, N, K, w->tune[key_prec], w->tune[P_F64], gr, exec});
+        w->graphs.push_back(
+            GraphEntry{u->uid, prm->solver, key_prec, N, K, c.mu, w->tune[key_prec], w->tune[P_F64], gr, exec});
       }
       LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;

@@ -311,8 +311,8 @@ class SolveResult:
 
 def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, maxiter=20000,
           solver=SOLVER_CG_EO, inner_prec=F64, reliable_every=100, use_graph=False, ws=None,
-          stream=None, psi=None, raise_on_noconv=True) -> SolveResult:
-    """Solve Dw psi = eta for canonical complex128 device source(s)."""
+          stream=None, psi=None, raise_on_noconv=True, mu=0.0) -> SolveResult:
+    """Solve D(mu) psi = eta (D(mu) = Dw + i mu g5) for canonical complex128 device source(s)."""
     lat = gauge.lat
     single = eta.dim() == 6
     e = eta.reshape((-1,) + lat.spinor_shape()).contiguous()
@@ -321,7 +321,7 @@ def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, m
         ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, nrhs)
     if psi is None:
         psi = torch.empty_like(e)
-    p = SolveParams(Dirac(float(kappa), float(csw), float(cF), 0.0), solver, inner_prec,
+    p = SolveParams(Dirac(float(kappa), float(csw), float(cF), float(mu)), solver, inner_prec,
                     int(reliable_every), int(maxiter), float(tol), nrhs, int(bool(use_graph)))
     infos = (SolveInfo * nrhs)()
     st = lib().lqcd_solve(gauge.handle, ctypes.byref(p), ctypes.c_void_p(e.data_ptr()),

@@ -1,0 +1,148 @@
+"""GPU parity of the twisted-mass operator D(mu) = Dw + i mu g5 against the
+oracle (clover_matrix(..., mu) and its true adjoint).
+
+Tolerances as for mu = 0: operators FP64 1e-12, FP32 2e-6, BF16 storage
+2e-2 (relative 2-norm); solves: oracle true residual <= 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2503_16994_amd import inputs, lqcd
+
+pytestmark = pytest.mark.gpu
+
+P, SF, OPEN = 0, 1, 2
+TH_AP = (1, 1, 1, -1)
+TH_RND = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.7])))
+TH_SPATIAL = tuple(np.exp(1j * np.array([0.3, -1.2, 2.2, 0.0])))
+MU = 0.071
+CASES = [
+    ((6, 4, 4, 6), P, TH_RND, 0.3, 0.1345, 1.9, 1.0),
+    ((4, 6, 4, 8), SF, TH_SPATIAL, 0.2, 0.134, 1.8, 1.3),
+    ((4, 4, 6, 6), OPEN, TH_SPATIAL, 0.2, 0.13, 1.9, 0.7),
+    ((8, 6, 4, 10), P, TH_AP, 0.2, 0.135, 1.9, 1.0),
+]
+PMASK = {lqcd.F64: lqcd.PM_F64, lqcd.F32: lqcd.PM_F64 | lqcd.PM_F32, lqcd.BF16: lqcd.PM_F64 | lqcd.PM_BF16}
+
+
+def case_id(c):
+    return f"{'x'.join(map(str, c[0]))}-{['P', 'SF', 'OPEN'][c[1]]}"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def g5(psi):
+    out = psi.copy()
+    out[..., 2:, :] *= -1
+    return out
+
+
+class TM:
+    def __init__(self, L, bc, theta, eps, kappa, csw, cF, seed=31, pm=lqcd.PM_F64, mu=MU):
+        self.L, self.bc, self.theta, self.kappa, self.csw, self.cF, self.mu = L, bc, theta, kappa, csw, cF, mu
+        self.U = inputs.gauge_field(L, eps, seed=seed, bc=bc)
+        m0 = orc.m0_from_kappa(kappa)
+        self.A = orc.clover_matrix(L, bc, self.U, m0, csw, cF, mu=mu)
+        self.Am = orc.clover_matrix(L, bc, self.U, m0, csw, cF, mu=-mu)
+        self.lat = lqcd.Lattice(L, bc, theta)
+        self.pm = pm
+        self.gauge = lqcd.GaugeField(self.lat, torch.from_numpy(self.U), pm)
+        self.d = lqcd.dirac(kappa, csw, cF, mu)
+
+    def o_dw(self, psi):
+        return orc.dw(self.L, self.bc, self.theta, self.U, self.A, psi)
+
+
+@pytest.mark.parametrize("split", [False, True], ids=["unsplit", "split"])
+@pytest.mark.parametrize("prec,tol", [(lqcd.F64, 1e-12), (lqcd.F32, 2e-6), (lqcd.BF16, 2e-2)],
+                         ids=["f64", "f32", "bf16"])
+@pytest.mark.parametrize("c", CASES, ids=case_id)
+def test_twisted_operators_match_oracle(c, prec, tol, split):
+    print(f"\n[gpu case] twisted {case_id(c)} prec {prec} split {split}", flush=True)
+    s = TM(*c, pm=PMASK[prec])
+    L, bc, th, U, A, Am = s.L, s.bc, s.theta, s.U, s.A, s.Am
+    Ai, Ami = orc.inverse_blocks(A), orc.inverse_blocks(Am)
+    odd = orc.parity_mask(L)
+    psi = inputs.gaussian_spinor(L, 5, bc)
+    pe = psi.copy()
+    pe[odd] = 0
+    po = psi.copy()
+    po[~odd] = 0
+    dh = orc.schur_dhat(L, bc, th, U, A, Ai, pe)
+    dw = orc.dw(L, bc, th, U, A, psi)
+    hop_oe = orc.apply_blocks(A, pe) - orc.hop(L, bc, th, U, po)
+    hop_oe[odd] = 0
+    if bc == SF:
+        hop_oe[0] = 0
+    refs = ((lqcd.OP_DW, dw), (lqcd.OP_DW_DAG, orc.dw_dag(L, bc, th, U, A, psi)),
+            (lqcd.OP_G5DW, g5(dw)), (lqcd.OP_DWDAGDW, orc.dw_dag(L, bc, th, U, A, dw)),
+            (lqcd.OP_HOP_EO, orc.schur_hop_eo(L, bc, th, U, Ai, pe)), (lqcd.OP_HOP_OE, hop_oe),
+            (lqcd.OP_SCHUR, dh), (lqcd.OP_SCHUR_DAG, g5(orc.schur_dhat(L, bc, th, U, Am, Ami, g5(pe)))),
+            (lqcd.OP_SCHUR_NORMAL, g5(orc.schur_dhat(L, bc, th, U, Am, Ami, g5(dh)))))
+    ws = lqcd.Workspace(s.lat, PMASK[prec], 1)
+    lqcd.set_tuning(ws, prec, nr_tile=3, block_order=2, rhs_lanes=1, dir_split=split)  # tile forced to 1
+    x = torch.from_numpy(np.ascontiguousarray(psi[None])).cuda()
+    for op, ref in refs:
+        got = lqcd.dw_apply(s.gauge, s.d, x, op=op, prec=prec, ws=ws)
+        torch.cuda.synchronize()
+        err = rel(got.cpu().numpy()[0], ref)
+        print(f"  op {op}: rel err {err:.3e}")
+        assert err < tol, (op, err)
+
+
+def _rho(s, eta, psi):
+    r = eta - s.o_dw(psi)
+    return float(np.linalg.norm(r) / np.linalg.norm(eta))
+
+
+@pytest.mark.parametrize("c", CASES[:3], ids=case_id)
+def test_twisted_eo_and_full_cg(c):
+    s = TM(*c, seed=23)
+    x0 = (0, 0, 0, 1) if s.bc == SF else (0, 0, 0, 0)
+    eta = np.stack([inputs.point_source(s.L, x0, 1, 2), inputs.gaussian_spinor(s.L, 9, s.bc)])
+    for solver in (lqcd.SOLVER_CG_EO, lqcd.SOLVER_CG_FULL):
+        r = lqcd.solve(s.gauge, torch.from_numpy(eta).cuda(), s.kappa, s.csw, s.cF, tol=1e-10, solver=solver,
+                       mu=s.mu)
+        assert r.status == lqcd.OK
+        psi = r.psi.cpu().numpy()
+        for j in range(2):
+            rho = _rho(s, eta[j], psi[j])
+            print(f"twisted {case_id(c)} solver {solver} rhs {j}: iters {r.info[j]['iters']} rho {rho:.3e}")
+            assert rho <= 1e-10
+
+
+@pytest.mark.parametrize("inner", [lqcd.F32, lqcd.BF16], ids=["f32", "bf16"])
+def test_twisted_mixed_multi_rhs_and_batch_equality(inner):
+    """12 point sources in one mixed solve with mu: every column within tol of
+    the oracle, and equal bit for bit to the same column solved alone."""
+    s = TM((8, 8, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=3, pm=PMASK[inner] | lqcd.PM_TWO_ROW)
+    eta = torch.from_numpy(inputs.point_sources_12(s.L, (0, 0, 0, 0))).cuda()
+    r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=inner, maxiter=20000, mu=s.mu)
+    assert r.status == lqcd.OK
+    psi = r.psi.cpu().numpy()
+    e = eta.cpu().numpy()
+    assert max(_rho(s, e[j], psi[j]) for j in range(12)) <= 1e-10
+    for j in (0, 7):
+        alone = lqcd.solve(s.gauge, eta[j:j + 1], s.kappa, s.csw, tol=1e-10, inner_prec=inner, maxiter=20000,
+                           mu=s.mu).psi.cpu().numpy()[0]
+        assert np.array_equal(alone, psi[j]), j
+
+
+def test_twisted_graph_cache_distinguishes_mu():
+    """Graph-captured solves with mu and then -mu on one workspace: each
+    solves its own system (a stale graph would replay the other sign)."""
+    c = CASES[3]
+    s = TM(*c, seed=41)
+    sm = TM(*c, seed=41, mu=-MU)
+    ws = lqcd.Workspace(s.lat, lqcd.PM_F64, 1)
+    eta = inputs.gaussian_spinor(s.L, 6)
+    stream = torch.cuda.Stream()
+    for t, mu in ((s, MU), (sm, -MU), (s, MU)):
+        r = lqcd.solve(s.gauge, torch.from_numpy(eta[None]).cuda(), t.kappa, t.csw, tol=1e-10, mu=mu,
+                       use_graph=True, ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        assert r.status == lqcd.OK and _rho(t, eta, r.psi.cpu().numpy()[0]) <= 1e-10, mu
