@@ -55,13 +55,14 @@ THETA = (1, 1, 1, -1)
 LINK_REALS = {True: 48, False: 72}  # per site V, two-row / full links
 
 
-def hop_reals(op, nrhs=1, two_row=True):
-    """Algorithmic reals per site V of one hop launch (or of the full Dw)."""
+def hop_reals(op, nrhs=1, two_row=True, tm=False):
+    """Algorithmic reals per site V of one hop launch (or of the full Dw);
+    tm: twisted mass, whose e->o launch also reads A_oo (36 reals per V)."""
     u = LINK_REALS[two_row]
     if op == "hop_oe":   # U + psi_o + psi_e + A_ee + out
         return u + 36 + 36 * nrhs
-    if op == "hop_eo":   # U + psi_e + A_oo^-1 + out
-        return u + 36 + 24 * nrhs
+    if op == "hop_eo":   # U + psi_e + A_oo^-1 (+ A_oo) + out
+        return u + 36 + (36 if tm else 0) + 24 * nrhs
     return u + 72 + 48 * nrhs  # full Dw: U + A + psi + out
 
 
@@ -76,6 +77,8 @@ DOMINANT_KERNEL = "k_hop<double2,double2,double2,PRE_CLOV,POST_NONE,HOP,1,1,SPLI
 STEP_TUNING = (1, 1, 1, True, True, 0, True)
 # gauge fields of every leg store two rows per link
 TWO_ROW = True
+# twisted mass of the twisted-mass leg (32^3x64 Z2 source)
+TM_MU = 0.01
 ROOFLINE_LAUNCHES = 100
 KERNEL_SOURCES = ["paper_2503_16994_amd/csrc/k_dslash.hip", "paper_2503_16994_amd/csrc/lqcd_dev.h"]
 
@@ -135,7 +138,8 @@ def hop_rates(g, lat_, ws, d, prec, nrhs, stream, reps=30):
         x = torch.randn(vb // 4, device="cuda").view(torch.uint8)
     y = torch.empty(vb, dtype=torch.uint8, device="cuda")
     tr = bool(g.pmask & lqcd.PM_TWO_ROW)
-    ops = [(lqcd.OP_HOP_EO, "hop_eo", hop_reals("hop_eo", nrhs, tr)),
+    tm = d.mu != 0.0
+    ops = [(lqcd.OP_HOP_EO, "hop_eo", hop_reals("hop_eo", nrhs, tr, tm)),
            (lqcd.OP_HOP_OE, "hop_oe", hop_reals("hop_oe", nrhs, tr))]
     if prec == lqcd.F64 and nrhs == 1:
         ops.append((lqcd.OP_DW, "dw_full", hop_reals("dw_full", 1, tr)))
@@ -430,6 +434,20 @@ def c3_leg(stream, pm, gpm, no_mixed, mixed_leg):
                     "true_residual": r.info[0]["true_residual"], "status": r.status}
         if name != "f64":
             c3[name]["vs_fp64"] = round(c3["f64"]["seconds"] / dt, 3)
+    # twisted mass D(mu) = Dw + i mu g5, same source
+    c3["twisted"] = {"mu": TM_MU}
+    for ip, name in precs:
+        def s3m():
+            return lqcd.solve(g3, eta3, kappa, CSW, tol=TOL, inner_prec=ip, reliable_every=100, use_graph=True,
+                              ws=ws3, stream=stream, raise_on_noconv=False, mu=TM_MU)
+        dt, r = timed(s3m, 2, 1)
+        c3["twisted"][name] = {"seconds": round(dt, 4), "iters": r.info[0]["iters"],
+                               "true_residual": r.info[0]["true_residual"], "status": r.status}
+        if name != "f64":
+            c3["twisted"][name]["vs_fp64"] = round(c3["twisted"]["f64"]["seconds"] / dt, 3)
+    d3m = lqcd.dirac(kappa, CSW, 1.0, TM_MU)
+    for k, v in hop_rates(g3, lat3, ws3, d3m, lqcd.F64, 1, stream).items():
+        dw_hbm[f"{k}_f64_twisted"] = dict(v, tuning=lqcd.get_tuning(ws3, lqcd.F64))
     log(f"C3: {c3}")
     del eta3
     # 12 point sources at the origin: FP64 one at a time, then 12 rhs per solve
