@@ -18,6 +18,8 @@
 // halving it the rhs is marked CG_STALLED and the host continues it in FP64
 // from the current solution.  Healthy solves gain about a factor ten per
 // update (the update is triggered by a tenfold drop of the recursive |r|).
+#include <algorithm>
+
 #include "lqcd_kernels.h"
 
 namespace lqcd {
@@ -383,7 +385,12 @@ hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nr
 
 hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, int nrhs, CGState* s,
                             void* plo, int lo_prec, const double* partials, int nparts, hipStream_t st) {
-  dim3 grid(blas_nblocks(n), nrhs);
+  // every workgroup re-sums its rhs's partials before streaming p: with many
+  // rhs, fewer workgroups per rhs (at least 256, each streaming more) keep
+  // that repeated sum small while the whole grid stays as large
+  const int nb = blas_nblocks(n);
+  const int nbx = std::min(nb, std::max(256, nb / nrhs));
+  dim3 grid(nbx, nrhs);
   if (prec == P_F64)
     k_cg_beta_p<double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
                                                        (double2*)nullptr, partials, nparts);

@@ -29,53 +29,100 @@ namespace lqcd {
 
 constexpr int kHopBlock = 128;  // threads per workgroup
 
-template <int MU, int DIR, int NR, typename A, typename SG, typename SI>
-__device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, const SI* yb, int p,
-                               int s, const Coord& c, int rhs0) {
-  const KGeom& g = a.g;
+// Raw operands of one hop (the link and the NR neighbour spinors, in their
+// storage types), so that a hop's loads can be issued before the arithmetic
+// of the hop before it.
+template <int NR, typename SG, typename SI>
+struct HopOperands {
+  SG u[9];
+  SI y[NR][12];
+};
+
+template <typename S>
+__device__ inline S raw_ld(const S* p) {
+  return *p;
+}
+__device__ inline double2 raw_ld_nt(const double2* p) {
+  nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ inline float2 raw_ld_nt(const float2* p) {
+  nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ inline bf16x2 raw_ld_nt(const bf16x2* p) {
+  return bf16x2{__builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p))};
+}
+template <typename A, typename S>
+__device__ inline cpx<A> widen(const S& v) {
+  const auto c = StoreTraits<S>::load(&v);
+  return {(A)c.re, (A)c.im};
+}
+
+// Phase of the hop x -> x + DIR mu at a site: the boundary phase on the edge,
+// zero where the hop is cut (the Schroedinger-functional backward hop from
+// t = 1 lands on the Dirichlet slice t = 0, whose field is ignored).
+template <int MU, int DIR, typename A>
+__device__ inline bool hop_phase(const KGeom& g, const Coord& c, bool& edge, A& pr, A& pi) {
   const int coord = coord_of(c, MU);
-  const bool edge = (DIR > 0) ? (coord == g.L[MU] - 1) : (coord == 0);
-  A pr = 1, pi = 0;
+  edge = (DIR > 0) ? (coord == g.L[MU] - 1) : (coord == 0);
+  pr = 1;
+  pi = 0;
   if (edge) {
     pr = (A)(DIR > 0 ? g.fwd_re[MU] : g.bwd_re[MU]);
     pi = (A)(DIR > 0 ? g.fwd_im[MU] : g.bwd_im[MU]);
   }
-  // Schroedinger functional: the backward hop from t = 1 lands on the
-  // Dirichlet slice t = 0, whose field is ignored.
-  if (MU == 3 && DIR < 0 && g.bc == BC_SF && c.t == 1) { pr = 0; pi = 0; }
-  if (pr == (A)0 && pi == (A)0) return;
+  if (MU == 3 && DIR < 0 && g.bc == BC_SF && c.t == 1) {
+    pr = 0;
+    pi = 0;
+  }
+  return !(pr == (A)0 && pi == (A)0);
+}
 
+template <int MU, int DIR, int NR, typename SG, typename SI>
+__device__ inline void hop_fetch(HopOperands<NR, SG, SI>& f, const HopLaunch& a, const SI* yb, int p, int s,
+                                 const Coord& c, int rhs0) {
+  const KGeom& g = a.g;
   const int sn = nb_index(g, s, c, MU, DIR);
   const int ne = a.two_row ? 6 : 9;                // stored complex per link
   const size_t par = (size_t)4 * ne * g.V2p;      // one parity of the link field
   const SG* Ub = static_cast<const SG*>(a.U);
   const SG* up = (DIR > 0) ? Ub + p * par + tix(s, 4 * ne) + MU * ne * kTile
                            : Ub + (1 - p) * par + tix(sn, 4 * ne) + MU * ne * kTile;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) f.u[e] = a.cached_gauge ? raw_ld(up + e * kTile) : raw_ld_nt(up + e * kTile);
+  if (!a.two_row) {
+#pragma unroll
+    for (int e = 6; e < 9; ++e) f.u[e] = a.cached_gauge ? raw_ld(up + e * kTile) : raw_ld_nt(up + e * kTile);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const SI* yp = yb + (size_t)(rhs0 + r) * a.y_rs + tix(sn, 12);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) f.y[r][k] = raw_ld(yp + k * kTile);
+  }
+}
+
+template <int MU, int DIR, int NR, typename A, typename SG, typename SI>
+__device__ inline void hop_apply(cpx<A> (&acc)[NR][4][3], const HopOperands<NR, SG, SI>& f, const HopLaunch& a,
+                                 const Coord& c) {
+  bool edge;
+  A pr, pi;
+  if (!hop_phase<MU, DIR, A>(a.g, c, edge, pr, pi)) return;
   cpx<A> U[9];
 #pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    auto v = a.cached_gauge ? ld(up + e * kTile) : ld_nt(up + e * kTile);
-    U[e] = {(A)v.re, (A)v.im};
-  }
+  for (int e = 0; e < 6; ++e) U[e] = widen<A>(f.u[e]);
   if (a.two_row) {
     su3_third_row(U);
   } else {
 #pragma unroll
-    for (int e = 6; e < 9; ++e) {
-      auto v = a.cached_gauge ? ld(up + e * kTile) : ld_nt(up + e * kTile);
-      U[e] = {(A)v.re, (A)v.im};
-    }
+    for (int e = 6; e < 9; ++e) U[e] = widen<A>(f.u[e]);
   }
-
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const SI* yp = yb + (size_t)(rhs0 + r) * a.y_rs + tix(sn, 12);
     cpx<A> psi[4][3];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      auto v = ld(yp + k * kTile);
-      psi[k / 3][k % 3] = {(A)v.re, (A)v.im};
-    }
+    for (int k = 0; k < 12; ++k) psi[k / 3][k % 3] = widen<A>(f.y[r][k]);
     cpx<A> h[2][3], w[2][3];
     spin_project<MU, DIR>(psi, h);
     if (DIR > 0) su3_mul(U, h, w);
@@ -90,6 +137,53 @@ __device__ inline void hop_dir(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, cons
     spin_accumulate<MU, DIR>(acc[r], w);
   }
 }
+
+// Hop k of the eight: direction k / 2, forward for even k.
+template <int K, int NR, typename SG, typename SI>
+__device__ inline void fetch_k(HopOperands<NR, SG, SI>& f, const HopLaunch& a, const SI* yb, int p, int s,
+                               const Coord& c, int rhs0) {
+  hop_fetch<K / 2, (K & 1) ? -1 : 1, NR, SG, SI>(f, a, yb, p, s, c, rhs0);
+}
+
+// Hops K .. K1-1 in order, one hop ahead: the loads of hop k+1 are issued
+// before the arithmetic of hop k (f[k & 1] holds hop k).  The accumulation
+// order is that of the plain sequence.
+template <int K, int K1, int NR, typename A, typename SG, typename SI>
+__device__ inline void hops_ahead(cpx<A> (&acc)[NR][4][3], HopOperands<NR, SG, SI> (&f)[2], const HopLaunch& a,
+                                  const SI* yb, int p, int s, const Coord& c, int rhs0) {
+  if constexpr (K + 1 < K1) fetch_k<K + 1>(f[(K + 1) & 1], a, yb, p, s, c, rhs0);
+  hop_apply<K / 2, (K & 1) ? -1 : 1, NR, A, SG, SI>(acc, f[K & 1], a, c);
+  if constexpr (K + 1 < K1) hops_ahead<K + 1, K1>(acc, f, a, yb, p, s, c, rhs0);
+}
+
+// Hops K0 .. K1-1 accumulated into acc.  With AHEAD the loads run one hop
+// ahead of the arithmetic (two hops' operands live in registers); without,
+// each hop loads and computes in turn and a cut hop loads nothing.
+template <bool AHEAD, int K0, int K1, int NR, typename A, typename SG, typename SI>
+__device__ inline void hop_range(cpx<A> (&acc)[NR][4][3], const HopLaunch& a, const SI* yb, int p, int s,
+                                 const Coord& c, int rhs0) {
+  if constexpr (AHEAD) {
+    HopOperands<NR, SG, SI> f[2];
+    fetch_k<K0>(f[K0 & 1], a, yb, p, s, c, rhs0);
+    hops_ahead<K0, K1>(acc, f, a, yb, p, s, c, rhs0);
+  } else {
+    HopOperands<NR, SG, SI> f;
+    bool edge;
+    A pr, pi;
+    if (hop_phase<K0 / 2, (K0 & 1) ? -1 : 1, A>(a.g, c, edge, pr, pi)) {
+      fetch_k<K0>(f, a, yb, p, s, c, rhs0);
+      hop_apply<K0 / 2, (K0 & 1) ? -1 : 1, NR, A, SG, SI>(acc, f, a, c);
+    }
+    if constexpr (K0 + 1 < K1) hop_range<false, K0 + 1, K1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+  }
+}
+
+// Loads one hop ahead where one hop's raw operands take at most 48 registers
+// per lane (BF16 with up to 3 rhs per thread, FP32 with one): the
+// reduced-precision multi-rhs launches are latency-bound, and FP64 would
+// give up too much occupancy.
+template <int NR, typename SG, typename SI>
+constexpr bool kHopAhead = 9 * sizeof(SG) + 12 * NR * sizeof(SI) <= 192;
 
 // out6 += i m in6 (m = +-mu: the twisted-mass term of one chirality block)
 template <typename A>
@@ -262,17 +356,13 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
   if (ts.active) {
     c = site_coord(g, s, p);
     if (HOP) {
-      if (!SPLIT || wv == 0) {
-        hop_dir<0, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<0, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<1, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<1, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-      }
-      if (!SPLIT || wv == 1) {
-        hop_dir<2, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<2, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<3, +1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
-        hop_dir<3, -1, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      constexpr bool AH = kHopAhead<NR, SG, SI>;
+      if (!SPLIT) {
+        hop_range<AH, 0, 8, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      } else if (wv == 0) {
+        hop_range<AH, 0, 4, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
+      } else {
+        hop_range<AH, 4, 8, NR, A, SG, SI>(acc, a, yb, p, s, c, rhs0);
       }
     }
   }
