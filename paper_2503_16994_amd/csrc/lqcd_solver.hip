@@ -33,6 +33,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -430,23 +431,26 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     if ((e = reliable_update())) return e;
     return launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st);
   };
-  constexpr int K = 10 * kRuStride;  // iterations per chunk (host poll / graph)
+  constexpr int K = 10 * kRuStride;      // iterations per chunk (host poll / graph)
+  constexpr int K_TAIL = 2 * kRuStride;  // chunk length near convergence
   const bool use_graph = prm->use_graph && st != nullptr;
-  // a chunk of K iterations, replayed from a graph cached in the workspace
-  // (keyed by everything the captured launches depend on)
-  auto run_chunk = [&]() -> int {
+  // a chunk of len iterations, replayed from a graph cached in the workspace
+  // (keyed by everything the captured launches depend on); chunk lengths
+  // are multiples of kRuStride, so the reliable-update slots keep their
+  // place in the iteration count whatever the mix of lengths
+  auto run_chunk = [&](const int len) -> int {
     if (use_graph) {
       const int key_prec = lo ? ip : LQCD_F64;
       hipGraphExec_t exec = nullptr;
       for (auto& e : w->graphs)
         if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == key_prec && e.nrhs == N &&
-            e.chunk == K && e.mu == c.mu && same_tuning(e.tune_inner, w->tune[key_prec]) &&
+            e.chunk == len && e.mu == c.mu && same_tuning(e.tune_inner, w->tune[key_prec]) &&
             same_tuning(e.tune_f64, w->tune[P_F64]))
           exec = e.exec;
       if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int i = 0; i < K && e == hipSuccess; ++i) e = iteration(i);
+        for (int i = 0; i < len && e == hipSuccess; ++i) e = iteration(i);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(st, &gr);
         if (e != hipSuccess) {
@@ -460,24 +464,33 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
           return hip_status(e3, "hipGraphInstantiate");
         }
         w->graphs.push_back(
-            GraphEntry{u->uid, prm->solver, key_prec, N, K, c.mu, w->tune[key_prec], w->tune[P_F64], gr, exec});
+            GraphEntry{u->uid, prm->solver, key_prec, N, len, c.mu, w->tune[key_prec], w->tune[P_F64], gr, exec});
       }
       LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;
     }
-    for (int i = 0; i < K; ++i) LQCD_HIP(iteration(i));
+    for (int i = 0; i < len; ++i) LQCD_HIP(iteration(i));
     return LQCD_OK;
   };
 
   std::vector<CGState> hs(N);
   const bool trace = getenv("LQCD_TRACE") != nullptr;  // per-chunk progress on stderr
-  const long max_chunks = (long)prm->maxiter / K + 3;
-  long chunk = 0;
-  // runs chunks until every rhs is done; returns whether one is CG_STALLED
+  const long max_launched = (long)prm->maxiter + 3L * K;
+  long launched = 0;  // iterations launched (done rhs skip theirs)
+  // runs chunks until every rhs is done; returns whether one is CG_STALLED.
+  // Chunks are K iterations long, or K_TAIL when every rhs still running is
+  // predicted to reach its inner target within half a chunk: the prediction
+  // extrapolates each rhs's |r|^2 decay rate since the previous poll, so the
+  // last chunk does not launch up to K - 1 iterations past convergence.  The
+  // chunk lengths change only when the host polls, never the arithmetic.
   auto run_phase = [&](bool& stalled) -> int {
     stalled = false;
-    for (;; ++chunk) {
-      int rc2 = run_chunk();
+    std::vector<double> rr_last(N, -1.0);
+    std::vector<int> it_last(N, 0);
+    int k_next = K;
+    for (;;) {
+      int rc2 = run_chunk(k_next);
+      launched += k_next;
       if (rc2) return rc2;
       LQCD_HIP(hipMemcpyAsync(hs.data(), cg, sizeof(CGState) * N, hipMemcpyDeviceToHost, st));
       LQCD_HIP(hipStreamSynchronize(st));
@@ -491,7 +504,24 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
                   hs[r].iters, hs[r].done, hs[r].status, hs[r].rr / hs[r].bnorm2, sqrt(hs[r].rho2),
                   hs[r].rupd, lo ? "" : " fp64");
       }
-      if (all_done || chunk >= max_chunks) return LQCD_OK;
+      if (all_done || launched >= max_launched) return LQCD_OK;
+      bool known = true;
+      double need = 0.0;  // predicted iterations to the slowest inner target
+      for (int r = 0; r < N; ++r) {
+        if (hs[r].done) continue;
+        const double rr = hs[r].rr;
+        const int di = hs[r].iters - it_last[r];
+        if (rr_last[r] > 0.0 && di > 0 && rr > 0.0 && rr < rr_last[r]) {
+          const double rate = log(rr / rr_last[r]) / di;  // < 0
+          if (rr > hs[r].target2) need = std::max(need, log(hs[r].target2 / rr) / rate);
+        } else {
+          known = false;
+        }
+        rr_last[r] = rr;
+        it_last[r] = hs[r].iters;
+      }
+      k_next = (known && need + kRuStride <= K / 2) ? K_TAIL : K;
+      if (trace) fprintf(stderr, "[lqcd] next chunk %d (predicted %.1f iterations, known %d)\n", k_next, need, known);
     }
   };
   bool stalled = false;
