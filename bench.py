@@ -282,12 +282,15 @@ def main():
         dict `hbm`, also the 12-rhs hop-kernel rates in each precision."""
         res = {}
         pmap = {"f64": lqcd.F64, "f32": lqcd.F32, "bf16": lqcd.BF16}
-        # the FP64 hops of the reliable updates run one rhs per thread: with
-        # the direction split (kept by the autotuner) they are ~25% faster
-        lqcd.set_tuning(ws, lqcd.F64, dir_split=True)
         for name in precs:
             ip = pmap[name]
             tune, _ = lqcd.autotune(g, lqcd.dirac(kappa, csw), ip, 12, ws, stream=stream)
+            if ip != lqcd.F64:
+                # the FP64 hops of the reliable updates run one rhs per thread:
+                # with the direction split they are ~25% faster
+                t64 = lqcd.get_tuning(ws, lqcd.F64)
+                t64["dir_split"] = True
+                lqcd.set_tuning(ws, lqcd.F64, **t64)
             if hbm is not None:
                 for k, v in hop_rates(g, lat_, ws, lqcd.dirac(kappa, csw), ip, 12, stream).items():
                     hbm[f"{k}_{name}_12rhs"] = dict(v, tuning=tune)
