@@ -482,10 +482,13 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   // predicted to reach its inner target within half a chunk: the prediction
   // extrapolates each rhs's |r|^2 decay rate since the previous poll, so the
   // last chunk does not launch up to K - 1 iterations past convergence.  The
-  // chunk lengths change only when the host polls, never the arithmetic.
+  // first poll of a phase predicts nothing: |r|^2 falls fastest in the first
+  // iterations, and a rate measured from iteration 0 would switch to short
+  // chunks (and extra polls) too early.  The chunk lengths change only when
+  // the host polls, never the arithmetic.
   auto run_phase = [&](bool& stalled) -> int {
     stalled = false;
-    std::vector<double> rr_last(N, -1.0);
+    std::vector<double> rr_last(N, -1.0);  // < 0: no previous point
     std::vector<int> it_last(N, 0);
     int k_next = K;
     for (;;) {

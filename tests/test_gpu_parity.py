@@ -256,6 +256,36 @@ def test_graph_capture_matches_eager_and_is_deterministic():
         assert np.array_equal(g.psi.cpu().numpy(), eager)
 
 
+def test_graph_chunks_of_both_lengths_match_eager(capfd, monkeypatch):
+    """Near convergence the solver switches from 50- to 10-iteration chunks
+    (a second cached graph; predicted from the |r|^2 decay between polls, so
+    only solves longer than 100 iterations can use it); the chunking never
+    changes a result: graph-captured 12-rhs BF16-inner solves on 16^3x32
+    (replayed three times, eager work in between) equal the eager solve bit
+    for bit, with equal iteration counts, and at tol 1e-10 (105 iterations)
+    the last chunk is a short one."""
+    s = Setup((16, 16, 16, 32), P, TH_AP, 0.2, 0.1345, 1.9, 1.0, seed=2,
+              pmask=lqcd.PM_F64 | lqcd.PM_BF16)
+    eta = torch.from_numpy(inputs.point_sources_12(s.L, (0, 0, 0, 0))).cuda()
+    stream = torch.cuda.Stream()
+    monkeypatch.setenv("LQCD_TRACE", "1")
+    seen = []
+    for tol in (1e-10, 1e-9):
+        ws = lqcd.Workspace(s.lat, s.gauge.pmask, 12)
+        eager = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=tol, inner_prec=lqcd.BF16, ws=ws, stream=stream)
+        torch.cuda.synchronize()
+        ref, iters = eager.psi.cpu().numpy(), [i["iters"] for i in eager.info]
+        for _ in range(3):
+            g = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=tol, inner_prec=lqcd.BF16, ws=ws, stream=stream,
+                           use_graph=True)
+            torch.cuda.synchronize()
+            assert g.status == lqcd.OK and [i["iters"] for i in g.info] == iters, tol
+            assert np.array_equal(g.psi.cpu().numpy(), ref), tol
+            lqcd.dw_apply(s.gauge, lqcd.dirac(s.kappa, s.csw), eta[:1], stream=stream)  # eager work between
+        seen.append((tol, max(iters), capfd.readouterr().err.count("next chunk 10")))
+    assert any(n > 0 for _, it, n in seen if it > 100), seen
+
+
 def test_tuning_does_not_change_results():
     """rhs tile, block order, rhs lanes, store and load kinds and occupancy caps
     leave every rhs bitwise equal."""
