@@ -255,7 +255,8 @@ int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
  * dividing nrhs, block_order, flags) of one Schur-operator application (both hop kernels)
  * in precision `prec` on nrhs fields of the workspace, with HIP events on
  * `stream`, at the workspace's real lattice shape; stores the fastest in the
- * workspace and returns it with its time in microseconds.  The
+ * workspace and in the process-wide tuning cache (below), and returns it with
+ * its time in microseconds.  The
  * LQCD_TUNE_DIR_SPLIT bit is the caller's choice and is kept as set in the
  * workspace; with it set only nr_tile = rhs_lanes = 1 (the shape it applies
  * to) is searched, so autotuning never changes a result.  Overwrites the
@@ -263,6 +264,30 @@ int lqcd_ws_get_tuning(const lqcd_ws_t *w, int prec, lqcd_tuning *t);
  * workspace's nrhs and `prec` held by gauge field and workspace. */
 int lqcd_autotune(const lqcd_gauge_t *u, const lqcd_dirac *d, int prec, int nrhs, lqcd_ws_t *w,
                   void *stream, lqcd_tuning *best, double *best_us);
+
+/* ---- tuning cache --------------------------------------------------------
+ * A process-wide table of autotuned configurations keyed by the device
+ * architecture (e.g. gfx950), the lattice extents and boundary type, the
+ * link storage (two rows or full), the precision, the rhs count, whether a
+ * twisted mass is set (twisted != 0) and the direction-split choice.
+ * lqcd_autotune adds its result; callers that must not tune while they run
+ * (a serving loop) look entries up, and the table can be written to and read
+ * from a text file so that later processes need not tune again.  No entry
+ * changes a result (except through the split bit, which is part of the key).
+ * Thread-safe. */
+/* OK with *t set, or ENOTFOUND. */
+int lqcd_tune_cache_find(const lqcd_gauge_t *u, int prec, int nrhs, int twisted, int dir_split,
+                         lqcd_tuning *t);
+/* Adds (or replaces) an entry; the split part of the key is t's
+ * LQCD_TUNE_DIR_SPLIT bit.  EINVAL for values out of range. */
+int lqcd_tune_cache_put(const lqcd_gauge_t *u, int prec, int nrhs, int twisted, const lqcd_tuning *t);
+int lqcd_tune_cache_size(void);
+void lqcd_tune_cache_clear(void);
+/* One line per entry; load adds a file's entries (replacing equal keys) and
+ * adds nothing if a line is malformed (EINVAL) or the file is missing
+ * (ENOTFOUND). */
+int lqcd_tune_cache_save(const char *path);
+int lqcd_tune_cache_load(const char *path);
 
 /* ---- solver (paper Sec. 3.3: CG!, propagator!) ------------------------- */
 enum {
@@ -282,6 +307,15 @@ typedef struct lqcd_solve_params {
   double tol;              /* target true relative residual |eta-Dw psi|/|eta| */
   int32_t nrhs;            /* number of right-hand sides solved together */
   int32_t use_graph;       /* capture iteration chunks in a hipGraph */
+  const void *x0;          /* initial guess (paper Sec. 3.3: CG! updates the
+                              solution field it is given): NULL starts from
+                              psi = 0; otherwise nrhs canonical complex128
+                              fields on the device (may be the psi argument
+                              itself: it is read before psi is written).  The
+                              first residual is an FP64 recomputation
+                              eta - Dw x0; a column whose x0 already meets tol
+                              takes no iteration.  In lqcd_submit x0 is a host
+                              buffer like eta. */
 } lqcd_solve_params;
 
 typedef struct lqcd_solve_info {
@@ -363,9 +397,23 @@ enum { LQCD_ECANCELED = -9 }; /* request cancelled by lqcd_server_destroy */
 int lqcd_server_create(void *arena, size_t arena_bytes, int max_streams, int queue_cap,
                        double sim_seconds, lqcd_server_t **out);
 /* Registers a gauge field: U is canonical complex128 in host memory, copied
- * into the arena in FP64 and the precisions of pmask.  Returns its id. */
+ * into the arena in FP64 and the precisions of pmask (on a stream of the
+ * server's own, not a worker's).  Returns its id.  Gauge fields are
+ * registered before requests are served: EBUSY while a request is queued or
+ * running, so that the arena left to admitted and queued requests never
+ * shrinks. */
 int lqcd_server_add_gauge(lqcd_server_t *s, const lqcd_geom_desc *desc, const void *U_host,
                           int pmask, int *gauge_id);
+/* Autotunes the hop kernels of gauge field gauge_id for requests of
+ * precision inner_prec with nrhs right-hand sides, on an otherwise idle GPU
+ * (a workspace borrowed from the arena, the server's own stream; no request
+ * is admitted meanwhile), and stores the result in the tuning cache.
+ * Requests never tune: each takes the cached tuning of its lattice, inner
+ * precision and rhs count (mu != 0 and the split bit as keys; the server
+ * never sets the split), else the default, and tunings never change a result.
+ * Does nothing if an entry exists.  EBUSY while a request is queued or
+ * running; ENOMEM if the arena has no room for the workspace. */
+int lqcd_server_warmup(lqcd_server_t *s, int gauge_id, int inner_prec, int nrhs);
 /* Device bytes one request with these parameters holds while it runs. */
 size_t lqcd_request_bytes(lqcd_server_t *s, int gauge_id, const lqcd_solve_params *p);
 /* Enqueues Dw psi = eta for gauge_id (thread-safe, non-blocking).  eta and

@@ -20,8 +20,8 @@ Sheikholeslami-Wohlert operator the paper cites):
 Functions with a pin in ``tests/test_oracle_pins.py``: ``gamma``,
 ``field_strength``, ``clover_matrix``, ``hop``, ``dw``, ``dw_dag``, ``cg``,
 ``schur_*``, ``su3_from_two_rows``, ``gamma_product``, ``meson_G``,
-``meson_correlator``, ``sf_source``, ``sf_correlators``.  None is "parity
-unpinned".
+``meson_correlator``, ``sf_source``, ``sf_correlators``, ``cg_fixed``,
+``singular_extremes``.  None is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -330,6 +330,77 @@ def sf_correlators(L, H):
     fP = 0.5 * np.einsum("jtxAa,jtxAa->t", Hm.conj(), Hm)
     fA = -0.5 * np.einsum("jtxAa,AB,jtxBa->t", Hm.conj(), gamma(3), Hm)
     return fP, fA
+
+
+def singular_extremes(L, bc, theta, U, A, seed=0, max_steps=300, rtol=1e-7, solve_tol=1e-12,
+                      op="full", want_max=True):
+    """Largest and smallest singular value of Dw on its active sites (every
+    site; with SF boundaries the slice t = 0 is excluded: the operator maps
+    it to zero and ignores it), or with op="schur" of the even-odd Schur
+    complement Dhat = A_ee - D_eo A_oo^{-1} D_oe on the active even sites,
+    for the error bound of a solve (|psi - psi_exact| / |psi_exact| <=
+    cond * rho with rho the true relative residual) and for the conditioning
+    of the normal equations (cond(D^+ D) = cond(D)^2).
+
+    sigma_max: power iteration on D^+ D (skipped with want_max=False: 0 is
+    returned); sigma_min: inverse iteration on D^+ D, each step
+    x = D^{-1} g5 D^{-1} g5 v (D^{-+} = g5 D^{-1} g5 for both operators).
+    Dw^{-1} is the oracle's CG to solve_tol; Dhat^{-1} v_e is the even part of
+    Dw^{-1} (v_e, 0) (block elimination of the odd sites).  Both iterations
+    stop when the Rayleigh quotient changes by less than rtol relative.
+    Returns (sigma_max, sigma_min, steps_max, steps_min); the inverse
+    iteration's sigma_min is an upper bound on the true one.
+    """
+    Lx, Ly, Lz, T = L
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (T, Lz, Ly, Lx, 4, 3)
+    odd = parity_mask(L)
+    schur = (op == "schur")
+    Ainv = inverse_blocks(A) if schur else None
+
+    def start():
+        v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        if bc == SF:
+            v[0] = 0
+        if schur:
+            v[odd] = 0
+        return v / np.linalg.norm(v)
+
+    def g5(v):
+        w = v.copy()
+        w[..., 2:, :] *= -1
+        return w
+
+    def fwd(v):
+        return schur_dhat(L, bc, theta, U, A, Ainv, v) if schur else dw(L, bc, theta, U, A, v)
+
+    def inv(v):
+        x = cg(L, bc, theta, U, A, v, solve_tol)[0]
+        return _restrict(x, ~odd) if schur else x
+
+    lam, steps_max = 0.0, 0
+    if want_max:
+        v = start()
+        for steps_max in range(1, max_steps + 1):
+            w = g5(fwd(g5(fwd(v))))  # D^+ D v
+            new = float(np.vdot(v, w).real)  # |D v|^2
+            v = w / np.linalg.norm(w)
+            if abs(new - lam) <= rtol * new:
+                lam = new
+                break
+            lam = new
+    v = start()
+    mu, steps_min = 0.0, 0
+    for steps_min in range(1, max_steps + 1):
+        z = g5(inv(g5(v)))  # D^{-+} v
+        x = inv(z)          # (D^+ D)^{-1} v
+        new = float(np.vdot(z, z).real)  # v^+ (D^+ D)^{-1} v
+        v = x / np.linalg.norm(x)
+        if abs(new - mu) <= rtol * new:
+            mu = new
+            break
+        mu = new
+    return float(np.sqrt(lam)), float(1.0 / np.sqrt(mu)), steps_max, steps_min
 
 
 def dense_dw(L, bc, theta, U, A) -> np.ndarray:

@@ -335,7 +335,19 @@ __global__ void k_cg_escalate(CGState* s, int n) {
   c.fp64_from = c.iters;
 }
 
+// a reliable update is pending for every rhs that is not done (the first
+// residual of a solve from an initial guess)
+__global__ void k_cg_force_ru(CGState* s, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  if (!s[r].done) s[r].skip_ru = 0;
+}
+
 // ---------------------------------------------------------------------------
+hipError_t launch_cg_force_ru(CGState* s, int nrhs, hipStream_t st) {
+  k_cg_force_ru<<<(nrhs + 63) / 64, 64, 0, st>>>(s, nrhs);
+  return hipGetLastError();
+}
 hipError_t launch_cg_escalate(CGState* s, int nrhs, hipStream_t st) {
   k_cg_escalate<<<(nrhs + 63) / 64, 64, 0, st>>>(s, nrhs);
   return hipGetLastError();

@@ -697,6 +697,7 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
     return hip_status(err, "lqcd_autotune");
   }
   w->tune[prec] = best_cfg;
+  tune_cache_put(u, prec, nrhs, d->mu != 0.0, best_cfg, best_t);
   if (best) *best = best_cfg;
   if (best_us) *best_us = best_t;
   return LQCD_OK;

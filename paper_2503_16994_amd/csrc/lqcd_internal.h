@@ -47,7 +47,7 @@ struct WsLayout {
   double* partials2 = nullptr; // [nrhs][max_parts]
   int max_parts = 0;
   lqcd::CGState* cg = nullptr; // [nrhs]
-  double* scal = nullptr;      // [4][nrhs]
+  double* scal = nullptr;      // [8][nrhs]
 };
 
 // A captured chunk of solver iterations, valid for the workspace's lifetime
@@ -91,6 +91,8 @@ int fail(int status, const char* fmt, ...);
 WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base);
 int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipStream_t st);
 int check_dirac(const lqcd_dirac* d);
+// adds an autotuning result to the process-wide tuning cache (lqcd_tune.hip)
+void tune_cache_put(const lqcd_gauge_t* u, int prec, int nrhs, int twisted, const lqcd_tuning& t, double us);
 
 inline int hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return LQCD_OK;

@@ -220,6 +220,8 @@ hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const
 // update (which recomputes r from x); every other rhs keeps its state and has
 // no pending update
 hipError_t launch_cg_escalate(CGState* s, int nrhs, hipStream_t st);
+// every rhs that is not done gets a pending reliable update
+hipError_t launch_cg_force_ru(CGState* s, int nrhs, hipStream_t st);
 
 // y = a*x + b*y  (element types by precision), per-rhs scalars not needed
 hipError_t launch_axpby(double a, const void* x, int xprec, double b, void* y, int yprec,

@@ -8,6 +8,12 @@
 // ones at most kMaxBypass times in a row.  All bookkeeping is host memory; the
 // device memory is the caller's arena.  In simulation mode (no arena) no HIP
 // call is made at all.
+//
+// Gauge fields are imported, and kernels autotuned (lqcd_server_warmup), on a
+// private stream while no request is queued or running: the arena space that
+// queued requests were admitted against never shrinks, and a tuning is never
+// timed on a GPU shared with requests.  A request reads the process-wide
+// tuning cache for its lattice, precision and rhs count and never tunes.
 #include <string.h>
 
 #include <algorithm>
@@ -103,13 +109,6 @@ struct Request {
   bool finished = false;  // set under the server lock once status/info are final
 };
 
-struct TuneKey {
-  int gauge_id, prec, nrhs;
-  bool operator<(const TuneKey& o) const {
-    return std::tie(gauge_id, prec, nrhs) < std::tie(o.gauge_id, o.prec, o.nrhs);
-  }
-};
-
 int request_pmask(const lqcd_solve_params* p) {
   return LQCD_PM_F64 | (p->inner_prec == LQCD_F32 ? LQCD_PM_F32 : 0) |
          (p->inner_prec == LQCD_BF16 ? LQCD_PM_BF16 : 0);
@@ -129,9 +128,11 @@ struct lqcd_server {
   std::vector<GaugeEntry> gauges;
   std::deque<Request*> queue;
   std::map<uint64_t, Request*> tickets;
-  std::map<TuneKey, lqcd_tuning> tuned;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  hipStream_t import_stream = nullptr;  // gauge import and warm-up tuning
+  int running = 0;                      // requests admitted and not finished
+  bool exclusive = false;               // gauge import or warm-up in progress: admit nothing
   bool stopping = false;
   bool stopped = false;
   uint64_t next_ticket = 1;
@@ -151,6 +152,7 @@ static size_t footprint(const lqcd_server* s, const GaugeEntry& g, const lqcd_so
 }
 
 Request* lqcd_server::pick_locked() {
+  if (exclusive) return nullptr;
   for (size_t i = 0; i < queue.size(); ++i) {
     Request* q = queue[i];
     size_t off;
@@ -182,33 +184,26 @@ void lqcd_server::run(Request* r, const GaugeEntry& g, int idx) {
   char* eta_dev = base + align_up(ws_bytes);
   char* psi_dev = eta_dev + align_up(canon);
   lqcd_ws_t* ws = nullptr;
-  int rc = lqcd_ws_create(g.geom, pm, r->p.nrhs, base, ws_bytes, &ws);
+  lqcd_solve_params p = r->p;
+  int rc = lqcd_ws_create(g.geom, pm, p.nrhs, base, ws_bytes, &ws);
   if (rc == LQCD_OK) {
-    // tuning per (gauge field, inner precision, nrhs): autotuned by the first
-    // request of that shape; tuning never changes a result
-    const int lp = r->p.inner_prec;
-    const TuneKey key{r->gauge_id, lp, r->p.nrhs};
-    bool have = false;
-    lqcd_tuning t{};
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      auto it = tuned.find(key);
-      if (it != tuned.end()) {
-        t = it->second;
-        have = true;
-      }
-    }
-    if (have) {
-      lqcd_ws_set_tuning(ws, lp, &t);
-    } else if (lqcd_autotune(g.gauge, &r->p.d, lp, r->p.nrhs, ws, st, &t, nullptr) == LQCD_OK) {
-      std::lock_guard<std::mutex> lk(mu);
-      tuned[key] = t;
-    }
+    // the cached tuning of this lattice, inner precision and rhs count, if
+    // lqcd_server_warmup (or an earlier lqcd_autotune) filled one; otherwise
+    // the default.  Never tuned here, and no tuning changes a result.
+    lqcd_tuning t;
+    if (lqcd_tune_cache_find(g.gauge, p.inner_prec, p.nrhs, p.d.mu != 0.0, 0, &t) == LQCD_OK)
+      lqcd_ws_set_tuning(ws, p.inner_prec, &t);
     hipError_t e = hipMemcpyAsync(eta_dev, r->eta, canon, hipMemcpyHostToDevice, st);
+    // an initial guess travels in the solution buffer (lqcd_solve reads x0
+    // before it writes psi)
+    if (e == hipSuccess && p.x0) {
+      e = hipMemcpyAsync(psi_dev, p.x0, canon, hipMemcpyHostToDevice, st);
+      p.x0 = psi_dev;
+    }
     if (e != hipSuccess) rc = hip_status(e, "request source upload");
   }
   if (rc == LQCD_OK) {
-    rc = lqcd_solve(g.gauge, &r->p, eta_dev, psi_dev, ws, st, r->info.data());
+    rc = lqcd_solve(g.gauge, &p, eta_dev, psi_dev, ws, st, r->info.data());
     if (rc == LQCD_OK || rc == LQCD_ENOCONV) {
       hipError_t e = hipMemcpyAsync(r->psi, psi_dev, canon, hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -232,6 +227,7 @@ void lqcd_server::worker(int idx) {
       continue;
     }
     r->t_admit = now();
+    ++running;
     const GaugeEntry g = gauges[r->gauge_id];  // copied under the lock
     lk.unlock();
     run(r, g, idx);
@@ -239,6 +235,7 @@ void lqcd_server::worker(int idx) {
     alloc.release(r->off, r->bytes);
     r->t_done = now();
     r->finished = true;
+    --running;
     cv.notify_all();
   }
 }
@@ -260,15 +257,19 @@ extern "C" int lqcd_server_create(void* arena, size_t arena_bytes, int max_strea
   s->queue_cap = queue_cap;
   s->alloc.init(arena_bytes & ~(kAlign - 1));
   if (!s->sim) {
-    for (int i = 0; i < max_streams; ++i) {
+    for (int i = 0; i <= max_streams; ++i) {  // one per worker, then the import stream
       hipStream_t st;
       hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
       if (e != hipSuccess) {
         for (auto x : s->streams) (void)hipStreamDestroy(x);
+        if (s->import_stream) (void)hipStreamDestroy(s->import_stream);
         delete s;
         return hip_status(e, "lqcd_server_create: stream");
       }
-      s->streams.push_back(st);
+      if (i < max_streams)
+        s->streams.push_back(st);
+      else
+        s->import_stream = st;
     }
   }
   for (int i = 0; i < max_streams; ++i) s->workers.emplace_back(&lqcd_server::worker, s, i);
@@ -292,6 +293,10 @@ extern "C" int lqcd_server_add_gauge(lqcd_server_t* s, const lqcd_geom_desc* des
   size_t tmp_off = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping || s->exclusive || s->running > 0 || !s->queue.empty()) {
+      lqcd_geom_free(geom);
+      return fail(LQCD_EBUSY, "lqcd_server_add_gauge: requests are queued or running");
+    }
     if (!s->alloc.alloc(g.bytes, &g.off)) {
       lqcd_geom_free(geom);
       return fail(LQCD_ENOMEM, "lqcd_server_add_gauge: arena full (%zu bytes needed)", g.bytes);
@@ -301,9 +306,13 @@ extern "C" int lqcd_server_add_gauge(lqcd_server_t* s, const lqcd_geom_desc* des
       lqcd_geom_free(geom);
       return fail(LQCD_ENOMEM, "lqcd_server_add_gauge: no room to stage the field");
     }
+    s->exclusive = true;  // nothing is admitted until the field is in place
+    // counted at once, so that a request submitted meanwhile is checked
+    // against the arena that will remain for requests
+    s->gauge_bytes_total += align_up(g.bytes);
   }
   if (!s->sim) {
-    hipStream_t st = s->streams[0];
+    hipStream_t st = s->import_stream;
     char* dev = s->arena + tmp_off;
     hipError_t e = hipMemcpyAsync(dev, U_host, canon, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
@@ -314,15 +323,64 @@ extern "C" int lqcd_server_add_gauge(lqcd_server_t* s, const lqcd_geom_desc* des
     s->alloc.release(tmp_off, canon);
     if (e != hipSuccess || rc != LQCD_OK) {
       s->alloc.release(g.off, g.bytes);
+      s->gauge_bytes_total -= align_up(g.bytes);
       lqcd_geom_free(geom);
+      s->exclusive = false;
+      s->cv.notify_all();
       return rc != LQCD_OK ? rc : hip_status(e, "lqcd_server_add_gauge");
     }
   }
   std::lock_guard<std::mutex> lk(s->mu);
   s->gauges.push_back(g);
-  s->gauge_bytes_total += align_up(g.bytes);
   *gauge_id = (int)s->gauges.size() - 1;
+  s->exclusive = false;
+  s->cv.notify_all();
   return LQCD_OK;
+}
+
+extern "C" int lqcd_server_warmup(lqcd_server_t* s, int gauge_id, int inner_prec, int nrhs) {
+  if (!s) return fail(LQCD_EINVAL, "lqcd_server_warmup: null server");
+  if (inner_prec < LQCD_F64 || inner_prec > LQCD_BF16 || nrhs < 1 || nrhs > 64)
+    return fail(LQCD_EINVAL, "lqcd_server_warmup: bad precision or nrhs");
+  GaugeEntry g;
+  size_t off = 0, bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (gauge_id < 0 || gauge_id >= (int)s->gauges.size())
+      return fail(LQCD_ENOTFOUND, "lqcd_server_warmup: unknown gauge id %d", gauge_id);
+    g = s->gauges[gauge_id];
+    if (!(g.pmask & (1 << inner_prec)))
+      return fail(LQCD_EINVAL, "lqcd_server_warmup: gauge field %d not stored in precision %d", gauge_id,
+                  inner_prec);
+    if (s->stopping || s->exclusive || s->running > 0 || !s->queue.empty())
+      return fail(LQCD_EBUSY, "lqcd_server_warmup: requests are queued or running");
+    if (s->sim) return LQCD_OK;
+    lqcd_tuning t;
+    if (lqcd_tune_cache_find(g.gauge, inner_prec, nrhs, 0, 0, &t) == LQCD_OK) return LQCD_OK;
+    const int pm = LQCD_PM_F64 | (inner_prec == LQCD_F32 ? LQCD_PM_F32 : 0) |
+                   (inner_prec == LQCD_BF16 ? LQCD_PM_BF16 : 0);
+    bytes = lqcd_ws_bytes(g.geom, pm, nrhs);
+    if (!s->alloc.alloc(bytes, &off))
+      return fail(LQCD_ENOMEM, "lqcd_server_warmup: no room for a %zu-byte workspace", bytes);
+    s->exclusive = true;  // the GPU stays idle apart from the tuning runs
+  }
+  const int pm = LQCD_PM_F64 | (inner_prec == LQCD_F32 ? LQCD_PM_F32 : 0) |
+                 (inner_prec == LQCD_BF16 ? LQCD_PM_BF16 : 0);
+  lqcd_ws_t* ws = nullptr;
+  int rc = lqcd_ws_create(g.geom, pm, nrhs, s->arena + off, bytes, &ws);
+  if (rc == LQCD_OK) {
+    // any Dirac parameters: the clover values do not change kernel timings
+    const lqcd_dirac d{0.13, 1.9, 1.0, 0.0};
+    rc = lqcd_autotune(g.gauge, &d, inner_prec, nrhs, ws, s->import_stream, nullptr, nullptr);
+    const hipError_t e = hipStreamSynchronize(s->import_stream);
+    if (rc == LQCD_OK && e != hipSuccess) rc = hip_status(e, "lqcd_server_warmup");
+    lqcd_ws_free(ws);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->alloc.release(off, bytes);
+  s->exclusive = false;
+  s->cv.notify_all();
+  return rc;
 }
 
 extern "C" size_t lqcd_request_bytes(lqcd_server_t* s, int gauge_id, const lqcd_solve_params* p) {
@@ -423,6 +481,7 @@ extern "C" int lqcd_server_destroy(lqcd_server_t* s, int cancel_pending) {
   if (!s) return fail(LQCD_EINVAL, "lqcd_server_destroy: null server");
   lqcd_server_stop(s, cancel_pending);
   for (auto st : s->streams) (void)hipStreamDestroy(st);
+  if (s->import_stream) (void)hipStreamDestroy(s->import_stream);
   for (auto& g : s->gauges) {
     if (g.gauge) lqcd_gauge_free(g.gauge);
     lqcd_geom_free(g.geom);

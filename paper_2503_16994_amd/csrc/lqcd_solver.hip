@@ -180,13 +180,22 @@ hipError_t hop_oe_xr(const Ctl& c, int lprec, Vec q, Vec t_o, Vec x, Vec r, Vec 
 // partial sums per rhs that the tuned iteration hops of precision lprec write
 int iter_parts(const Ctl& c, int lprec) { return hop_nparts(mk(c, lprec)); }
 
+// the launch shape of dw_full (both parities, the FP64 tuning)
+HopLaunch dw_full_launch(const Ctl& c) {
+  HopLaunch h = mk(c, P_F64);
+  h.both = true;
+  return h;
+}
+// partial sums per rhs that a dw_full launch writes (its own site blocks:
+// the tuned rhs tile and direction split decide the block size)
+int full_parts(const Ctl& c) { return hop_nparts(dw_full_launch(c)); }
+
 // out (full, both parities) = [g5] Dw y, optional partials
 hipError_t dw_full(const Ctl& c, const double2* y, double2* out, bool g5, double* partials,
                    const int* done) {
-  HopLaunch h = mk(c, P_F64);
+  HopLaunch h = dw_full_launch(c);
   const long V2 = c.g->V2p;  // field rows per parity
   h.in_prec = h.out_prec = P_F64;
-  h.both = true;
   h.par_stride = 12 * V2;
   h.cpre_par = 36 * V2;
   h.y = y;
@@ -275,30 +284,39 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   const bool mixed = eo && ip != LQCD_F64;
   const double tol = prm->tol;
 
-  // ---- validate the source: finite, and zero on the SF Dirichlet slice ----
+  // ---- validate the source (and x0): finite, and zero on the SF Dirichlet slice
   double* parts = m.partials;
   double* parts2 = m.partials2;
-  double* scal = m.scal;  // [0,N) |b|^2  [N,2N) |eta|^2  [2N,3N) |eta(t=0)|^2  [3N,4N) final
+  // [0,N) |b|^2  [N,2N) |eta|^2  [2N,3N) |eta(t=0)|^2  [3N,4N) final residual^2
+  // [4N,5N) |x0|^2  [5N,6N) |x0(t=0)|^2
+  double* scal = m.scal;
   std::vector<double> h_eta2(N);
+  const void* x0 = prm->x0;
   {
     const long nsite = g->V * 12;
-    LQCD_HIP(launch_norm2(eta, P_F64, nsite, nsite, N, parts, st));
-    LQCD_HIP(launch_reduce(parts, blas_nblocks(nsite), N, scal + N, st));
     const bool sf = g->desc.bc == LQCD_BC_SF;
-    if (sf) {
-      const long nslice = g->V / g->desc.L[3] * 12;  // t = 0 is the first slice
-      LQCD_HIP(launch_norm2(eta, P_F64, nslice, nsite, N, parts, st));
-      LQCD_HIP(launch_reduce(parts, blas_nblocks(nslice), N, scal + 2 * N, st));
-    }
-    std::vector<double> tmp(2 * N, 0.0);
-    LQCD_HIP(hipMemcpyAsync(tmp.data(), scal + N, sizeof(double) * (sf ? 2 * N : N),
-                            hipMemcpyDeviceToHost, st));
+    const long nslice = g->V / g->desc.L[3] * 12;  // t = 0 is the first slice
+    auto norms = [&](const void* v, double* dst_all, double* dst_t0) -> hipError_t {
+      hipError_t e = launch_norm2(v, P_F64, nsite, nsite, N, parts, st);
+      if (e == hipSuccess) e = launch_reduce(parts, blas_nblocks(nsite), N, dst_all, st);
+      if (e == hipSuccess && sf) e = launch_norm2(v, P_F64, nslice, nsite, N, parts, st);
+      if (e == hipSuccess && sf) e = launch_reduce(parts, blas_nblocks(nslice), N, dst_t0, st);
+      return e;
+    };
+    LQCD_HIP(norms(eta, scal + N, scal + 2 * N));
+    if (x0) LQCD_HIP(norms(x0, scal + 4 * N, scal + 5 * N));
+    std::vector<double> tmp(6 * N, 0.0);
+    LQCD_HIP(hipMemcpyAsync(tmp.data(), scal, sizeof(double) * 6 * N, hipMemcpyDeviceToHost, st));
     LQCD_HIP(hipStreamSynchronize(st));
     for (int r = 0; r < N; ++r) {
-      h_eta2[r] = tmp[r];
-      if (!isfinite(tmp[r])) return fail(LQCD_ENUMERIC, "lqcd_solve: source %d has NaN/Inf entries", r);
-      if (sf && tmp[N + r] != 0.0)
+      h_eta2[r] = tmp[N + r];
+      if (!isfinite(tmp[N + r])) return fail(LQCD_ENUMERIC, "lqcd_solve: source %d has NaN/Inf entries", r);
+      if (sf && tmp[2 * N + r] != 0.0)
         return fail(LQCD_EINVAL, "lqcd_solve: source %d is non-zero on the SF boundary slice t=0", r);
+      if (x0 && !isfinite(tmp[4 * N + r]))
+        return fail(LQCD_ENUMERIC, "lqcd_solve: initial guess %d has NaN/Inf entries", r);
+      if (x0 && sf && tmp[5 * N + r] != 0.0)
+        return fail(LQCD_EINVAL, "lqcd_solve: initial guess %d is non-zero on the SF boundary slice t=0", r);
     }
   }
 
@@ -315,7 +333,10 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   const int nb_hop = hop_nparts(h1);
 
   LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
-  LQCD_HIP(launch_fill_zero(m.X, full_bytes, st));
+  if (x0)
+    LQCD_HIP(launch_pack(g->kg, (const double2*)x0, m.X, P_F64, N, false, st));
+  else
+    LQCD_HIP(launch_fill_zero(m.X, full_bytes, st));
 
   // b = Dhat^+ eta_hat (eo) or Dw^+ eta (full) into R, with |b|^2
   int nb_op;  // partial count of the norm-producing operator launch
@@ -332,7 +353,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   } else {
     LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.Q, P_F64, N, true, st));  // g5 eta
     LQCD_HIP(dw_full(dg(c), m.Q, m.R, true, parts, nullptr));
-    nb_op = 2 * nb_hop;
+    nb_op = full_parts(c);
   }
   LQCD_HIP(launch_reduce(parts, nb_op, N, scal, st));
 
@@ -396,8 +417,18 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
     if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, N, cg, parts2, st))) return e;
     if ((e = dw_full(dg(c), m.AP, m.R, true, parts, skip_ru))) return e;
-    return launch_ru_finish(cg, parts2, blas_nblocks(24 * V2), parts, 2 * nb_hop, N, st);
+    return launch_ru_finish(cg, parts2, blas_nblocks(24 * V2), parts, full_parts(c), N, st);
   };
+
+  // ---- initial guess: the first residual comes from a reliable update ------
+  // (r = Dhat^+ (eta_hat - Dhat x0) in FP64, or Dw^+ (eta - Dw x0); an rhs
+  // whose x0 already meets tol is done), then p = r
+  if (x0) {
+    LQCD_HIP(launch_cg_force_ru(cg, N, st));
+    LQCD_HIP(reliable_update());
+    void* plo = lo16 ? pin.p : nullptr;
+    LQCD_HIP(launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, lo16 ? P_BF16 : P_F32, st));
+  }
 
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
   // eo: hop, hop (+g5, |Dhat p|^2), hop (+alpha), hop fused with the x/r

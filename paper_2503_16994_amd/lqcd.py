@@ -61,7 +61,8 @@ class Dirac(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("d", Dirac), ("solver", ctypes.c_int32), ("inner_prec", ctypes.c_int32),
                 ("reliable_every", ctypes.c_int32), ("maxiter", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("nrhs", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tol", ctypes.c_double), ("nrhs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("x0", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -111,7 +112,14 @@ SIGNATURES = {
     "lqcd_ws_get_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
     "lqcd_autotune": (_I, [_P, ctypes.POINTER(Dirac), _I, _I, _P, _P, ctypes.POINTER(Tuning),
                            ctypes.POINTER(ctypes.c_double)]),
+    "lqcd_tune_cache_find": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(Tuning)]),
+    "lqcd_tune_cache_put": (_I, [_P, _I, _I, _I, ctypes.POINTER(Tuning)]),
+    "lqcd_tune_cache_size": (_I, []),
+    "lqcd_tune_cache_clear": (None, []),
+    "lqcd_tune_cache_save": (_I, [ctypes.c_char_p]),
+    "lqcd_tune_cache_load": (_I, [ctypes.c_char_p]),
     "lqcd_server_create": (_I, [_P, _Z, _I, _I, _D, ctypes.POINTER(_P)]),
+    "lqcd_server_warmup": (_I, [_P, _I, _I, _I]),
     "lqcd_server_add_gauge": (_I, [_P, ctypes.POINTER(GeomDesc), _P, _I, ctypes.POINTER(_I)]),
     "lqcd_request_bytes": (_Z, [_P, _I, ctypes.POINTER(SolveParams)]),
     "lqcd_submit": (_I, [_P, _I, ctypes.POINTER(SolveParams), _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
@@ -157,6 +165,43 @@ def _dev_bytes(nbytes: int) -> torch.Tensor:
 def _aligned_ptr(t: torch.Tensor) -> int:
     p = t.data_ptr()
     return (p + 255) & ~255
+
+
+def _spinor_arg(name: str, t: torch.Tensor, lat, nrhs=None) -> torch.Tensor:
+    """Checks a canonical spinor argument before its pointer crosses the ABI:
+    complex128, on the GPU, a whole number of fields (nrhs of them if given);
+    returns it as a contiguous (nrhs, T, Z, Y, X, 4, 3) tensor."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (device) tensor")
+    per = 1
+    for v in lat.spinor_shape():
+        per *= v
+    if t.numel() == 0 or t.numel() % per:
+        raise ValueError(f"{name} holds {t.numel()} elements, not a multiple of one field ({per})")
+    if nrhs is not None and t.numel() != nrhs * per:
+        raise ValueError(f"{name} holds {t.numel() // per} fields, expected {nrhs}")
+    return t.reshape((-1,) + lat.spinor_shape()).contiguous()
+
+
+def _out_arg(name: str, t: torch.Tensor, like: torch.Tensor, others=()) -> torch.Tensor:
+    """Checks a caller-supplied output: complex128 device tensor of exactly
+    like's shape, contiguous (written in place), overlapping none of `others`."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.numel() != like.numel():
+        raise ValueError(f"{name} holds {t.numel()} elements, expected {like.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (it is written in place)")
+    nb = t.numel() * t.element_size()
+    for o in others:
+        ob = o.numel() * o.element_size()
+        if t.data_ptr() < o.data_ptr() + ob and o.data_ptr() < t.data_ptr() + nb:
+            raise ValueError(f"{name} overlaps an input")
+    return t.reshape(like.shape)
 
 
 def m0_from_kappa(kappa: float) -> float:
@@ -254,12 +299,13 @@ def dw_apply(gauge: GaugeField, d: Dirac, psi: torch.Tensor, op=OP_DW, prec=F64,
     """Apply an operator to canonical complex128 device field(s)."""
     lat = gauge.lat
     single = psi.dim() == 6
-    x = psi.reshape((-1,) + lat.spinor_shape()).contiguous()
+    x = _spinor_arg("psi", psi, lat)
     nrhs = x.shape[0]
     if ws is None:
         ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, nrhs)
-    if out is None:
-        out = torch.empty_like(x)
+    if nrhs > ws.nrhs:
+        raise ValueError(f"{nrhs} fields exceed the workspace's {ws.nrhs}")
+    out = torch.empty_like(x) if out is None else _out_arg("out", out, x, (x,))
     _check(lib().lqcd_dw_apply(gauge.handle, ctypes.byref(d), op, prec, LAYOUT_CANON, nrhs,
                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                ws.handle, _stream_ptr(stream)))
@@ -269,6 +315,16 @@ def dw_apply(gauge: GaugeField, d: Dirac, psi: torch.Tensor, op=OP_DW, prec=F64,
 def dw_apply_internal(gauge: GaugeField, d: Dirac, vin: torch.Tensor, vout: torch.Tensor, op, prec,
                       nrhs, ws: Workspace, stream=None):
     """Apply an operator to internal-layout vectors (benchmarking)."""
+    need = vec_bytes(gauge.lat, prec, nrhs, 2)
+    for name, v in (("vin", vin), ("vout", vout)):
+        if not isinstance(v, torch.Tensor) or not v.is_cuda or not v.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CUDA tensor")
+        if v.numel() * v.element_size() < need:
+            raise ValueError(f"{name} holds {v.numel() * v.element_size()} bytes, {need} needed")
+    if vin.data_ptr() == vout.data_ptr():
+        raise ValueError("vin and vout must differ")
+    if nrhs > ws.nrhs:
+        raise ValueError(f"{nrhs} fields exceed the workspace's {ws.nrhs}")
     _check(lib().lqcd_dw_apply(gauge.handle, ctypes.byref(d), op, prec, LAYOUT_INTERNAL, nrhs,
                                ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(vout.data_ptr()),
                                ws.handle, _stream_ptr(stream)))
@@ -298,6 +354,33 @@ def autotune(gauge: GaugeField, d: Dirac, prec, nrhs, ws: Workspace, stream=None
     return t.as_dict(), us.value
 
 
+def tune_cache_find(gauge: GaugeField, prec, nrhs, twisted=False, dir_split=False):
+    """The cached tuning dict for this key, or None."""
+    t = Tuning()
+    st = lib().lqcd_tune_cache_find(gauge.handle, int(prec), int(nrhs), int(bool(twisted)), int(bool(dir_split)),
+                                    ctypes.byref(t))
+    if st == ENOTFOUND:
+        return None
+    _check(st)
+    return t.as_dict()
+
+
+def tune_cache_size() -> int:
+    return int(lib().lqcd_tune_cache_size())
+
+
+def tune_cache_clear():
+    lib().lqcd_tune_cache_clear()
+
+
+def tune_cache_save(path: str):
+    _check(lib().lqcd_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str):
+    _check(lib().lqcd_tune_cache_load(os.fsencode(path)))
+
+
 def vec_bytes(lat: Lattice, prec, nrhs, nparity=2) -> int:
     return int(lib().lqcd_vec_bytes(lat.handle, prec, nrhs, nparity))
 
@@ -311,18 +394,24 @@ class SolveResult:
 
 def solve(gauge: GaugeField, eta: torch.Tensor, kappa, csw, cF=1.0, tol=1e-10, maxiter=20000,
           solver=SOLVER_CG_EO, inner_prec=F64, reliable_every=100, use_graph=False, ws=None,
-          stream=None, psi=None, raise_on_noconv=True, mu=0.0) -> SolveResult:
-    """Solve D(mu) psi = eta (D(mu) = Dw + i mu g5) for canonical complex128 device source(s)."""
+          stream=None, psi=None, raise_on_noconv=True, mu=0.0, x0=None) -> SolveResult:
+    """Solve D(mu) psi = eta (D(mu) = Dw + i mu g5) for canonical complex128 device source(s),
+    from the initial guess x0 (same shape as eta; None: zero)."""
     lat = gauge.lat
     single = eta.dim() == 6
-    e = eta.reshape((-1,) + lat.spinor_shape()).contiguous()
+    e = _spinor_arg("eta", eta, lat)
     nrhs = e.shape[0]
     if ws is None:
         ws = Workspace(lat, gauge.pmask & PM_PRECISIONS, nrhs)
-    if psi is None:
-        psi = torch.empty_like(e)
+    if nrhs > ws.nrhs:
+        raise ValueError(f"{nrhs} sources exceed the workspace's {ws.nrhs}")
+    x0p = None
+    if x0 is not None:
+        x0 = _spinor_arg("x0", x0, lat, nrhs)
+        x0p = ctypes.c_void_p(x0.data_ptr())
+    psi = torch.empty_like(e) if psi is None else _out_arg("psi", psi, e, (e,))
     p = SolveParams(Dirac(float(kappa), float(csw), float(cF), float(mu)), solver, inner_prec,
-                    int(reliable_every), int(maxiter), float(tol), nrhs, int(bool(use_graph)))
+                    int(reliable_every), int(maxiter), float(tol), nrhs, int(bool(use_graph)), x0p)
     infos = (SolveInfo * nrhs)()
     st = lib().lqcd_solve(gauge.handle, ctypes.byref(p), ctypes.c_void_p(e.data_ptr()),
                           ctypes.c_void_p(psi.data_ptr()), ws.handle, _stream_ptr(stream), infos)
@@ -420,6 +509,10 @@ class Server:
         _check(lib().lqcd_server_add_gauge(self.handle, ctypes.byref(d), ptr, int(pmask), ctypes.byref(gid)))
         return gid.value
 
+    def warmup(self, gauge_id, inner_prec, nrhs):
+        """Autotune the kernels for (gauge field, inner precision, nrhs) on the idle GPU."""
+        _check(lib().lqcd_server_warmup(self.handle, int(gauge_id), int(inner_prec), int(nrhs)))
+
     @staticmethod
     def params(kappa, csw, cF=1.0, tol=1e-10, maxiter=20000, inner_prec=F64, nrhs=1, reliable_every=100,
                use_graph=True):
@@ -429,23 +522,34 @@ class Server:
     def request_bytes(self, gauge_id, p: SolveParams) -> int:
         return int(lib().lqcd_request_bytes(self.handle, int(gauge_id), ctypes.byref(p)))
 
-    def submit(self, gauge_id, p: SolveParams, eta=None, psi=None) -> int:
-        """Enqueue a solve; eta/psi are host complex128 arrays (kept alive here)."""
+    def submit(self, gauge_id, p: SolveParams, eta=None, psi=None, x0=None) -> int:
+        """Enqueue a solve; eta/psi (and the initial guess x0) are host complex128
+        arrays of p.nrhs fields (kept alive here until the final poll)."""
+        import numpy as np
         ep = pp = None
         if eta is not None:
-            import numpy as np
             eta = np.ascontiguousarray(eta, dtype=np.complex128)
             if psi is None:
                 psi = np.empty_like(eta)
+            if psi.dtype != np.complex128 or psi.shape != eta.shape or not psi.flags.c_contiguous:
+                raise ValueError("psi must be a C-contiguous complex128 array shaped like eta")
             ep, pp = ctypes.c_void_p(eta.ctypes.data), ctypes.c_void_p(psi.ctypes.data)
+        if x0 is not None:
+            if eta is None:
+                raise ValueError("x0 needs eta")
+            x0 = np.ascontiguousarray(x0, dtype=np.complex128)
+            if x0.shape != eta.shape:
+                raise ValueError("x0 must be shaped like eta")
+            p = SolveParams.from_buffer_copy(p)
+            p.x0 = x0.ctypes.data
         t = ctypes.c_uint64(0)
         _check(lib().lqcd_submit(self.handle, int(gauge_id), ctypes.byref(p), ep, pp, ctypes.byref(t)))
-        self._live[t.value] = (eta, psi, p.nrhs)
+        self._live[t.value] = (eta, psi, p.nrhs, x0)
         return t.value
 
     def poll(self, ticket):
         """None while pending; else (status, [info dicts], (t_submit, t_admit, t_done), psi)."""
-        eta, psi, nrhs = self._live[ticket]
+        eta, psi, nrhs, _ = self._live[ticket]
         infos = (SolveInfo * nrhs)()
         times = (ctypes.c_double * 3)()
         st = lib().lqcd_poll(self.handle, ctypes.c_uint64(ticket), infos, times)

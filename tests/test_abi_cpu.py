@@ -150,3 +150,53 @@ def test_tuning_values_are_validated():
     assert lib.lqcd_meson(g, None, 1, pairs, fake, None, w, None) == lqcd.EINVAL
     lib.lqcd_ws_free(w)
     lib.lqcd_geom_free(g)
+
+
+def test_tuning_cache_file_round_trip(tmp_path):
+    """The tuning-cache text format: a file of valid entries loads (and
+    replaces equal keys), saves back line for line; a malformed line makes
+    the load fail with EINVAL and add nothing; a missing file is ENOTFOUND."""
+    from paper_2503_16994_amd import lqcd
+    lqcd.tune_cache_clear()
+    lines = ["gfx950 32 32 32 64 0 1 2 12 0 0 3 2 1 1 812.500",
+             "gfx950 16 16 16 32 0 1 0 1 0 1 1 1 1 19 25.125"]
+    src = tmp_path / "t.txt"
+    src.write_text("# lqcd tuning cache v1\n" + "\n".join(lines) + "\n")
+    lqcd.tune_cache_load(str(src))
+    assert lqcd.tune_cache_size() == 2
+    lqcd.tune_cache_load(str(src))  # same keys: replaced, not added
+    assert lqcd.tune_cache_size() == 2
+    out = tmp_path / "u.txt"
+    lqcd.tune_cache_save(str(out))
+    got = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    assert sorted(got) == sorted(lines)
+    bad = tmp_path / "bad.txt"
+    bad.write_text(lines[0] + "\n" + "gfx950 8 8 8 8 0 1 2 12 0 0 9 2 1 1 1.0\n")  # nr_tile 9
+    with pytest.raises(lqcd.LqcdError) as e:
+        lqcd.tune_cache_load(str(bad))
+    assert e.value.status == lqcd.EINVAL
+    split_mismatch = tmp_path / "split.txt"
+    split_mismatch.write_text("gfx950 8 8 8 8 0 1 0 1 0 0 1 1 1 16 1.0\n")  # split bit set, key says 0
+    with pytest.raises(lqcd.LqcdError):
+        lqcd.tune_cache_load(str(split_mismatch))
+    assert lqcd.tune_cache_size() == 2
+    with pytest.raises(lqcd.LqcdError) as e:
+        lqcd.tune_cache_load(str(tmp_path / "missing.txt"))
+    assert e.value.status == lqcd.ENOTFOUND
+    lqcd.tune_cache_clear()
+    assert lqcd.tune_cache_size() == 0
+
+
+def test_binding_argument_checks_without_a_gpu():
+    """The binding's checks of spinor arguments run before any pointer
+    crosses the ABI (here on CPU tensors: they fail as not on the device)."""
+    import torch
+    from paper_2503_16994_amd import lqcd
+    lat = lqcd.Lattice((4, 4, 4, 4), lqcd.BC_PERIODIC, (1, 1, 1, -1))
+    good = torch.zeros((1,) + lat.spinor_shape(), dtype=torch.complex128)
+    with pytest.raises(TypeError):
+        lqcd._spinor_arg("eta", good.to(torch.complex64), lat)
+    with pytest.raises(ValueError):
+        lqcd._spinor_arg("eta", good, lat)  # a host tensor
+    with pytest.raises(TypeError):
+        lqcd._spinor_arg("eta", good.numpy(), lat)

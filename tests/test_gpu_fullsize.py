@@ -117,12 +117,22 @@ def c4():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("inner", [lqcd.F64, lqcd.BF16], ids=["f64", "bf16"])
+@pytest.mark.parametrize("inner", [lqcd.F64, lqcd.F32, lqcd.BF16], ids=["f64", "f32", "bf16"])
 def test_multi_rhs_24x24x24x48_sf_twelve_sources(c4, inner):
+    """The 24^3x48 SF workload: the 12 point sources at t = 1 in one 12-rhs
+    solve, FP64, FP32 or BF16 inner precision with FP64 reliable updates
+    every 100 iterations, autotuned kernels, graph chunks, and the FP64 hops
+    of the reliable updates with the direction split (the benchmark's mixed
+    legs); every column's residual recomputed by the oracle <= 1e-10."""
     L, kappa, csw, th = c4["L"], c4["kappa"], c4["csw"], c4["th"]
+    print(f"\n[gpu case] 24^3x48 SF 12 rhs inner {inner}", flush=True)
     ws = lqcd.Workspace(c4["lat"], PM, 12)
     d = lqcd.dirac(kappa, csw)
     best, _ = lqcd.autotune(c4["g"], d, inner, 12, ws)
+    if inner != lqcd.F64:
+        t64 = lqcd.get_tuning(ws, lqcd.F64)
+        t64["dir_split"] = True
+        lqcd.set_tuning(ws, lqcd.F64, **t64)
     eta = inputs.point_sources_12(L, (0, 0, 0, 1))
     stream = torch.cuda.Stream()
     r = lqcd.solve(c4["g"], torch.from_numpy(eta).cuda(), kappa, csw, tol=1e-10, inner_prec=inner,

@@ -656,3 +656,103 @@ def test_twisted_mass_cg_and_schur_against_dense_solve(L, bc):
     xe[eidx] = np.linalg.solve(Dh[eidx], eh[eidx])
     full = orc.schur_reconstruct(L, bc, theta, U, Ainv, eta, xe.reshape(shape))
     assert rel(full.reshape(-1), ref) < 1e-12
+
+
+def _dense_active(L, bc, theta, U, A):
+    """Dense Dw restricted to its active sites (SF: without the slice t = 0)."""
+    M = orc.dense_dw(L, bc, theta, U, A)
+    if bc != SF:
+        return M, np.arange(M.shape[0])
+    act = np.ones(tuple(L[::-1]) + (4, 3), bool)
+    act[0] = False
+    idx = np.flatnonzero(act.reshape(-1))
+    return M[np.ix_(idx, idx)], idx
+
+
+@pytest.mark.parametrize("L,bc", [((2, 2, 2, 2), PERIODIC), ((2, 2, 2, 4), SF)])
+def test_cg_fixed_iterates_minimise_the_residual_over_the_krylov_space(L, bc):
+    """cg_fixed after k steps (CG on the normal equations, paper Sec. 3.3 CG!)
+    is the minimiser of |eta - Dw psi| over span{b, M b, ..., M^(k-1) b},
+    M = Dw^+ Dw, b = Dw^+ eta: computed here by least squares on an
+    orthonormal Krylov basis built from the dense matrix, a route that shares
+    none of the CG recursion.  A wrong alpha, beta or residual update moves
+    the iterate off that minimiser.  Its return value is |M psi - b| / |b|."""
+    U, A, theta = _setup(L, bc, seed=21, eps=0.3, cF=1.0, m0=0.2)
+    x0 = (0, 0, 0, 1) if bc == SF else (0, 0, 0, 0)
+    eta = inputs.point_source(L, x0, 0, 1) + 0.3 * inputs.gaussian_spinor(L, 8, bc)
+    D, idx = _dense_active(L, bc, theta, U, A)
+    e = eta.reshape(-1)[idx]
+    M = D.conj().T @ D
+    b = D.conj().T @ e
+    for k in (1, 2, 3, 5):
+        psi, ret = orc.cg_fixed(L, bc, theta, U, A, eta, k)
+        got = psi.reshape(-1)[idx]
+        K = np.empty((b.size, k), complex)
+        v = b.copy()
+        for j in range(k):
+            K[:, j] = v
+            v = M @ v
+        Q, _ = np.linalg.qr(K)
+        c, *_ = np.linalg.lstsq(D @ Q, e, rcond=None)
+        ref = Q @ c
+        assert rel(got, ref) < 1e-10, (k, rel(got, ref))
+        normal_res = np.linalg.norm(M @ got - b) / np.linalg.norm(b)
+        assert abs(ret - normal_res) <= 1e-10 * max(normal_res, 1e-3), (k, ret, normal_res)
+    # k = dim steps: the dense solve (CG terminates in exact arithmetic)
+    psi, _ = orc.cg_fixed(L, bc, theta, U, A, eta, b.size)
+    assert rel(psi.reshape(-1)[idx], np.linalg.solve(D, e)) < 1e-8
+
+
+def test_cg_fixed_equals_cg_without_restart():
+    """On a system that converges without a restart, cg_fixed with cg's own
+    iteration count reproduces cg's solution (the bench's CPU baseline times
+    cg_fixed as a stand-in for cg)."""
+    L, bc = (4, 4, 4, 4), PERIODIC
+    U, A, theta = _setup(L, bc, seed=5, eps=0.2, cF=1.0, m0=0.5)
+    eta = inputs.point_source(L, (0, 0, 0, 0), 2, 0)
+    psi, rho, iters, ok = orc.cg(L, bc, theta, U, A, eta, tol=1e-10)
+    assert ok
+    psi_f, _ = orc.cg_fixed(L, bc, theta, U, A, eta, iters)
+    assert rel(psi_f, psi) < 1e-12
+
+
+@pytest.mark.parametrize("L,bc", [((2, 2, 2, 2), PERIODIC), ((2, 2, 2, 4), SF), ((2, 2, 2, 4), OPEN)])
+def test_singular_extremes_against_dense_svd(L, bc):
+    """Power and inverse iteration (singular_extremes) against numpy's dense
+    SVD of Dw on its active sites, and of the Schur complement
+    Dhat = A_ee - D_eo A_oo^{-1} D_oe assembled densely from the blocks of
+    the dense Dw (numpy.linalg.solve for the odd block)."""
+    U, A, theta = _setup(L, bc, seed=31, eps=0.3, cF=1.2, m0=0.05)
+    smax, smin, _, _ = orc.singular_extremes(L, bc, theta, U, A, max_steps=2000, rtol=1e-12)
+    D, idx = _dense_active(L, bc, theta, U, A)
+    s = np.linalg.svd(D, compute_uv=False)
+    assert abs(smax - s[0]) <= 1e-6 * s[0], (smax, s[0])
+    assert abs(smin - s[-1]) <= 1e-6 * s[-1], (smin, s[-1])
+    # Schur complement on the even sites
+    odd = np.broadcast_to(orc.parity_mask(L)[..., None, None], tuple(L[::-1]) + (4, 3)).reshape(-1)[idx]
+    e, o = np.flatnonzero(~odd), np.flatnonzero(odd)
+    Dh = D[np.ix_(e, e)] - D[np.ix_(e, o)] @ np.linalg.solve(D[np.ix_(o, o)], D[np.ix_(o, e)])
+    sh = np.linalg.svd(Dh, compute_uv=False)
+    hmax, hmin, _, _ = orc.singular_extremes(L, bc, theta, U, A, max_steps=2000, rtol=1e-12, op="schur")
+    assert abs(hmax - sh[0]) <= 1e-6 * sh[0], (hmax, sh[0])
+    assert abs(hmin - sh[-1]) <= 1e-6 * sh[-1], (hmin, sh[-1])
+
+
+def test_schroedinger_functional_at_kappa_0134_is_ill_conditioned():
+    """The conditioning behind the mixed-precision behaviour of the 24^3x48
+    SF workload (kappa 0.134, csw 1.8, near-free links eps 0.2): on a 4^3x8
+    lattice with the same parameters cond(Dhat) is several times that of the
+    periodic lattice at the same kappa and of the SF lattice at
+    kappa 0.125, and cond(Dhat^+ Dhat) = cond(Dhat)^2 grows with the volume
+    (a 6^3x12 estimate, 20 min of CPU, is quoted in the design notes)."""
+    L = (4, 4, 4, 8)
+    conds = {}
+    for name, bc, kappa in (("sf_0134", SF, 0.134), ("sf_0125", SF, 0.125), ("p_0134", PERIODIC, 0.134)):
+        U = inputs.gauge_field(L, 0.2, seed=4, bc=bc)
+        th = (1, 1, 1, 1) if bc == SF else (1, 1, 1, -1)
+        A = orc.clover_matrix(L, bc, U, orc.m0_from_kappa(kappa), 1.8, 1.0)
+        smax, smin, _, _ = orc.singular_extremes(L, bc, th, U, A, max_steps=200, rtol=1e-5, op="schur")
+        conds[name] = smax / smin
+    print({k: round(v, 1) for k, v in conds.items()}, "cond^2 * 2^-24 =", conds["sf_0134"] ** 2 * 2.0 ** -24)
+    assert conds["sf_0134"] > 3 * conds["sf_0125"]
+    assert conds["sf_0134"] > 3 * conds["p_0134"]

@@ -91,6 +91,7 @@ def test_small_requests_pass_a_blocked_head_with_bounded_bypass():
 def test_queue_limit_oversize_and_unknown_ids():
     srv = _server(1 << 30, streams=1, cap=2, sim=0.3)
     g = srv.add_gauge(L8, 0, TH)
+    big_lat = srv.add_gauge((16, 16, 16, 32), 0, TH)
     p = lqcd.Server.params(0.13, 1.9)
     t1 = srv.submit(g, p)
     time.sleep(0.05)  # t1 admitted, queue empty
@@ -103,7 +104,6 @@ def test_queue_limit_oversize_and_unknown_ids():
         srv.submit(g + 7, p)
     assert e.value.status == lqcd.ENOTFOUND
     huge = lqcd.Server.params(0.13, 1.9, nrhs=64)
-    big_lat = srv.add_gauge((16, 16, 16, 32), 0, TH)
     with pytest.raises(lqcd.LqcdError) as e:
         srv.submit(big_lat, huge)
     assert e.value.status == lqcd.ENOMEM
@@ -139,4 +139,29 @@ def test_stop_without_cancel_runs_the_queue():
     ts = [srv.submit(g, p) for _ in range(6)]
     srv.stop(cancel_pending=False)
     assert all(srv.poll(t)[0] == lqcd.OK for t in ts)
+    srv.close()
+
+
+def test_gauge_fields_and_warmup_only_while_idle():
+    """Registering a gauge field or tuning while a request is queued or
+    running is refused (EBUSY): the arena left to admitted and queued
+    requests never shrinks, and tunings are never timed under load."""
+    srv = _server(1 << 30, streams=1, cap=8, sim=0.3)
+    g = srv.add_gauge(L8, 0, TH)
+    srv.warmup(g, lqcd.F64, 1)  # idle: accepted (nothing to tune in simulation)
+    p = lqcd.Server.params(0.13, 1.9)
+    ts = [srv.submit(g, p) for _ in range(2)]
+    time.sleep(0.05)  # one running, one queued
+    for call in (lambda: srv.add_gauge((8, 8, 8, 16), 0, TH), lambda: srv.warmup(g, lqcd.F64, 1)):
+        with pytest.raises(lqcd.LqcdError) as e:
+            call()
+        assert e.value.status == lqcd.EBUSY
+    res = _wait(srv, ts)
+    assert all(r[0] == lqcd.OK for r in res.values())
+    g2 = srv.add_gauge((8, 8, 8, 16), 0, TH)  # idle again
+    t = srv.submit(g2, p)
+    assert _wait(srv, [t])[t][0] == lqcd.OK
+    with pytest.raises(lqcd.LqcdError) as e:
+        srv.warmup(g2 + 5, lqcd.F64, 1)
+    assert e.value.status == lqcd.ENOTFOUND
     srv.close()
