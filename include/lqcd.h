@@ -209,6 +209,27 @@ size_t lqcd_vec_bytes(const lqcd_geom_t *g, int prec, int nrhs, int nparity);
 int lqcd_meson(const lqcd_geom_t *g, const void *psi, int npairs, const int32_t *pairs, void *C, void *G,
                lqcd_ws_t *w, void *stream);
 
+/* ---- entry points that allocate nothing -------------------------------- */
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  Their scratch memory is one fixed device array of the
+ * library per GPU, LQCD_NOALLOC_SCRATCH_BYTES long, that each GPU the library
+ * runs on holds until the process ends.  Every call on a GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (two streams, two
+ * threads) race and give wrong results; serialise them.  The array keeps the
+ * last call's contents, which no call reads before writing. */
+#define LQCD_NOALLOC_SCRATCH_BYTES (32u << 20)
+size_t lqcd_noalloc_scratch_bytes(void);
+
+/* lqcd_meson without a workspace: same arguments, results and errors, and
+ * the same kernels, with the T x ceil(Lx Ly Lz / 256) x 256 complex128
+ * partials in the fixed array instead of the workspace (32^3x64 needs all
+ * 32 MiB).  EINVAL, without device work, for a lattice whose partials exceed
+ * LQCD_NOALLOC_SCRATCH_BYTES.  Calls no allocating routine; the first call
+ * on a device looks up the array's address there (EDEVICE if that fails). */
+int lqcd_meson_noalloc(const lqcd_geom_t *g, const void *psi, int npairs, const int32_t *pairs, void *C,
+                       void *G, void *stream);
+
 /* ---- kernel tuning (autotuner) ------------------------------------------ */
 typedef struct lqcd_tuning {
   int32_t nr_tile;     /* right-hand sides per thread in the hop kernels: 1..3

@@ -542,21 +542,35 @@ extern "C" int lqcd_dw_apply(const lqcd_gauge_t* u, const lqcd_dirac* d, int op,
 // ---------------------------------------------------------------------------
 // meson two-point functions
 // ---------------------------------------------------------------------------
+namespace lqcd {
+int meson_check(const char* who, const lqcd_geom_t* g, const void* psi, int npairs, const int32_t* pairs,
+                const void* C, const void* G) {
+  if (!g || !psi) return fail(LQCD_EINVAL, "%s: null pointer", who);
+  if (npairs < 0 || npairs > kMaxMesonPairs)
+    return fail(LQCD_EINVAL, "%s: npairs=%d (0..%d)", who, npairs, kMaxMesonPairs);
+  if (npairs > 0 && (!pairs || !C)) return fail(LQCD_EINVAL, "%s: pairs and C needed for npairs > 0", who);
+  if (npairs == 0 && !G) return fail(LQCD_EINVAL, "%s: nothing to compute (no pairs, no G)", who);
+  for (int p = 0; p < 2 * npairs; ++p)
+    if (pairs[p] < 0 || pairs[p] > 15) return fail(LQCD_EINVAL, "%s: gamma mask %d (0..15)", who, pairs[p]);
+  if (((uintptr_t)psi & 15) || ((uintptr_t)C & 15) || ((uintptr_t)G & 15))
+    return fail(LQCD_EINVAL, "%s: misaligned device pointer", who);
+  return LQCD_OK;
+}
+
+size_t meson_scratch_bytes(const lqcd_geom_t* g) {
+  const long V3 = (long)g->desc.L[0] * g->desc.L[1] * g->desc.L[2];
+  return (size_t)g->desc.L[3] * meson_nchunk(V3) * 256 * sizeof(double2);
+}
+}  // namespace lqcd
+
 extern "C" int lqcd_meson(const lqcd_geom_t* g, const void* psi, int npairs, const int32_t* pairs, void* C,
                           void* G, lqcd_ws_t* w, void* stream) {
-  if (!g || !psi || !w) return fail(LQCD_EINVAL, "lqcd_meson: null pointer");
-  if (npairs < 0 || npairs > kMaxMesonPairs)
-    return fail(LQCD_EINVAL, "lqcd_meson: npairs=%d (0..%d)", npairs, kMaxMesonPairs);
-  if (npairs > 0 && (!pairs || !C)) return fail(LQCD_EINVAL, "lqcd_meson: pairs and C needed for npairs > 0");
-  if (npairs == 0 && !G) return fail(LQCD_EINVAL, "lqcd_meson: nothing to compute (no pairs, no G)");
-  for (int p = 0; p < 2 * npairs; ++p)
-    if (pairs[p] < 0 || pairs[p] > 15) return fail(LQCD_EINVAL, "lqcd_meson: gamma mask %d (0..15)", pairs[p]);
+  if (!w) return fail(LQCD_EINVAL, "lqcd_meson: null pointer");
+  const int rc = meson_check("lqcd_meson", g, psi, npairs, pairs, C, G);
+  if (rc) return rc;
   if (w->g != g && memcmp(&w->g->desc, &g->desc, sizeof(lqcd_geom_desc)) != 0)
     return fail(LQCD_EINVAL, "lqcd_meson: workspace of another geometry");
-  if (((uintptr_t)psi & 15) || ((uintptr_t)C & 15) || ((uintptr_t)G & 15))
-    return fail(LQCD_EINVAL, "lqcd_meson: misaligned device pointer");
-  const long V3 = (long)g->desc.L[0] * g->desc.L[1] * g->desc.L[2];
-  const size_t need = (size_t)g->desc.L[3] * meson_nchunk(V3) * 256 * sizeof(double2);
+  const size_t need = meson_scratch_bytes(g);
   const size_t have = (size_t)8 * w->nrhs * 24 * g->V2p * sizeof(double2);  // the FP64 vectors E..EH
   if (need > have) return fail(LQCD_EINVAL, "lqcd_meson: workspace scratch %zu < %zu bytes", have, need);
   double2* outs[kMaxMesonPairs];

@@ -91,6 +91,11 @@ int fail(int status, const char* fmt, ...);
 WsLayout plan_ws(const lqcd_geom_t* g, int pmask, int nrhs, char* base);
 int ensure_clover(const lqcd_gauge_t* u, const lqcd_dirac* d, lqcd_ws_t* w, hipStream_t st);
 int check_dirac(const lqcd_dirac* d);
+// argument checks shared by the meson entry points (status, last error set)
+int meson_check(const char* who, const lqcd_geom_t* g, const void* psi, int npairs, const int32_t* pairs,
+                const void* C, const void* G);
+// FP64 complex partials of the meson contraction: T x chunks x 256 entries
+size_t meson_scratch_bytes(const lqcd_geom_t* g);
 // adds an autotuning result to the process-wide tuning cache (lqcd_tune.hip)
 void tune_cache_put(const lqcd_gauge_t* u, int prec, int nrhs, int twisted, const lqcd_tuning& t, double us);
 

@@ -106,6 +106,8 @@ SIGNATURES = {
     "lqcd_vec_bytes": (_Z, [_P, _I, _I, _I]),
     "lqcd_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "lqcd_meson": (_I, [_P, _P, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]),
+    "lqcd_meson_noalloc": (_I, [_P, _P, _I, ctypes.POINTER(ctypes.c_int32), _P, _P, _P]),
+    "lqcd_noalloc_scratch_bytes": (_Z, []),
     "lqcd_sf_source": (_I, [_P, _P, _P]),
     "lqcd_sf_correlators": (_I, [_P, ctypes.POINTER(SolveParams), _P, _P, _P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "lqcd_ws_set_tuning": (_I, [_P, _I, ctypes.POINTER(Tuning)]),
@@ -430,8 +432,8 @@ def meson(lat: Lattice, psi: torch.Tensor, pairs, ws: Workspace, want_G=True, st
     complex128, shape (12, T, Z, Y, X, 4, 3)): returns (C, G) with C of shape
     (len(pairs), T) and G of shape (T, 4, 4, 4, 4) (None unless want_G)."""
     p = psi.contiguous()
-    if p.dtype != torch.complex128 or p.numel() != 12 * lat.volume * 12:
-        raise ValueError("psi must be 12 canonical complex128 fields")
+    if p.dtype != torch.complex128 or not p.is_cuda or p.numel() != 12 * lat.volume * 12:
+        raise ValueError("psi must be 12 canonical complex128 fields on the GPU")
     T = lat.L[3]
     n = len(pairs)
     flat = (ctypes.c_int32 * max(2 * n, 1))(*[int(m) for pr in pairs for m in pr])
@@ -441,6 +443,31 @@ def meson(lat: Lattice, psi: torch.Tensor, pairs, ws: Workspace, want_G=True, st
                             ctypes.c_void_p(C.data_ptr() if C is not None else 0),
                             ctypes.c_void_p(G.data_ptr() if G is not None else 0), ws.handle, _stream_ptr(stream)))
     return C, G
+
+
+def meson_noalloc(lat: Lattice, psi: torch.Tensor, pairs, C=None, G=None, stream=None):
+    """lqcd_meson_noalloc: the contraction of ``meson`` with the library's
+    fixed per-GPU scratch array instead of a workspace.  The caller passes
+    the outputs: C (complex128, (len(pairs), T)) and/or G (complex128,
+    (T, 4, 4, 4, 4)), contiguous device tensors, written in place."""
+    if psi.dtype != torch.complex128 or not psi.is_cuda or not psi.is_contiguous() \
+            or psi.numel() != 12 * lat.volume * 12:
+        raise ValueError("psi must be 12 contiguous canonical complex128 fields on the GPU")
+    T = lat.L[3]
+    n = len(pairs)
+    for name, t, shape in (("C", C, (n, T)), ("G", G, (T, 4, 4, 4, 4))):
+        if t is not None and (t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous()
+                              or tuple(t.shape) != shape):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {shape}")
+    flat = (ctypes.c_int32 * max(2 * n, 1))(*[int(m) for pr in pairs for m in pr])
+    _check(lib().lqcd_meson_noalloc(lat.handle, ctypes.c_void_p(psi.data_ptr()), n, flat,
+                                    ctypes.c_void_p(C.data_ptr() if C is not None else 0),
+                                    ctypes.c_void_p(G.data_ptr() if G is not None else 0), _stream_ptr(stream)))
+    return C, G
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().lqcd_noalloc_scratch_bytes())
 
 
 def sf_source(gauge: GaugeField, stream=None) -> torch.Tensor:

@@ -200,3 +200,26 @@ def test_binding_argument_checks_without_a_gpu():
         lqcd._spinor_arg("eta", good, lat)  # a host tensor
     with pytest.raises(TypeError):
         lqcd._spinor_arg("eta", good.numpy(), lat)
+
+
+def test_meson_noalloc_rejects_lattices_beyond_its_fixed_scratch_without_device_work():
+    """The fixed scratch array holds the partials of 32^3x64 exactly; a lattice
+    with more slices or more chunks per slice is refused before any device
+    call (the device pointers below are never dereferenced)."""
+    lqcd, lib = _lib()
+    assert lib.lqcd_noalloc_scratch_bytes() == 32 << 20
+    pairs = (ctypes.c_int32 * 2)(15, 15)
+    fake = ctypes.c_void_p(1 << 20)
+    for L, ok in (((32, 32, 32, 64), True), ((32, 32, 32, 66), False), ((32, 32, 34, 64), False)):
+        g = ctypes.c_void_p()
+        assert lib.lqcd_geom(ctypes.byref(_desc(lqcd, L)), ctypes.byref(g)) == lqcd.OK
+        # 32^3x64 passes the size check; it is only asserted through the
+        # bound arithmetic here, since a passing call would launch kernels
+        need = L[3] * ((L[0] * L[1] * L[2] + 255) // 256) * 256 * 16
+        assert (need <= lib.lqcd_noalloc_scratch_bytes()) == ok
+        if not ok:
+            assert lib.lqcd_meson_noalloc(g, fake, 1, pairs, fake, None, None) == lqcd.EINVAL
+            assert b"scratch bytes" in lib.lqcd_last_error()
+        assert lib.lqcd_meson_noalloc(g, None, 1, pairs, fake, None, None) == lqcd.EINVAL
+        assert lib.lqcd_meson_noalloc(g, fake, 33, pairs, fake, None, None) == lqcd.EINVAL
+        lib.lqcd_geom_free(g)
