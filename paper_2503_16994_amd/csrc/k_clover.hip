@@ -10,9 +10,11 @@
 // This is the sigma_{mu nu} (x) F_{mu nu} sum written out for the chiral
 // basis (sigma_{kl} = -eps_{klm} diag(s_m, s_m), sigma_{tk} = diag(s_k, -s_k)).
 // The inverse of each block on the odd sites is formed by an unpivoted
-// LDL^H factorisation (the blocks are Hermitian and, for the parameters the
-// solver is used with, far from singular; a pivot below 1e-12 of the block
-// scale is reported as a numerical error).
+// LDL^H factorisation, with Gauss-Jordan elimination under partial pivoting
+// as the fallback for an indefinite block with a tiny LDL^H pivot
+// (clover_inv.h); a block that is singular to working precision is reported
+// as a numerical error.
+#include "clover_inv.h"
 #include "lqcd_kernels.h"
 
 namespace lqcd {
@@ -175,62 +177,6 @@ __device__ inline void store_packed(S* field, size_t s, int c0, const cd (&B)[6]
     for (int j = 0; j < i; ++j) st(base + tri_index(i, j) * kTile, B[i][j]);
 }
 
-// Inverse of a Hermitian 6x6 block by LDL^H; returns false on a tiny pivot.
-__device__ inline bool herm6_inverse(const cd (&A)[6][6], cd (&R)[6][6]) {
-  cd L[6][6];
-  double D[6];
-  double scale = 0.0;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) scale = fmax(scale, fabs(A[i][i].re));
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double dj = A[j][j].re;
-#pragma unroll
-    for (int k = 0; k < j; ++k) dj -= (L[j][k].re * L[j][k].re + L[j][k].im * L[j][k].im) * D[k];
-    if (!(fabs(dj) > 1e-12 * scale)) ok = false;
-    D[j] = dj;
-    const double inv = 1.0 / dj;
-#pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
-      cd v = A[i][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) {
-        cd t = cmulc(L[j][k], L[i][k]);  // L_ik conj(L_jk)
-        v = csub(v, cscale(D[k], t));
-      }
-      L[i][j] = cscale(inv, v);
-    }
-  }
-  // X = L^{-1} (unit lower triangular)
-  cd X[6][6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < 6; ++j) X[i][j] = {i == j ? 1.0 : 0.0, 0.0};
-#pragma unroll
-  for (int i = 1; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < i; ++j) {
-      cd v = {0.0, 0.0};
-#pragma unroll
-      for (int k = j; k < i; ++k) v = cadd(v, cmul(L[i][k], X[k][j]));
-      X[i][j] = {-v.re, -v.im};
-    }
-  // A^{-1} = X^+ D^{-1} X
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      cd v = {0.0, 0.0};
-#pragma unroll
-      for (int k = i; k < 6; ++k) v = cadd(v, cscale(1.0 / D[k], cmulc(X[k][i], X[k][j])));
-      R[i][j] = v;
-      R[j][i] = {v.re, -v.im};
-    }
-  return ok;
-}
-
 __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
   const KGeom& g = c.g;
   const int p = blockIdx.y;
@@ -273,7 +219,7 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
     if (c.C16) store_packed(c.C16 + par, s, 18 * b, B);
     if (p == 1 && c.mu == 0.0) {
       cd R[6][6];
-      if (!herm6_inverse(B, R)) atomicOr(c.err_flag, 1);
+      if (blk6::herm_inverse(B, R) == blk6::INV_SINGULAR) atomicOr(c.err_flag, 1);
       store_packed(c.Ci64, s, 18 * b, R);
       if (c.Ci32) store_packed(c.Ci32, s, 18 * b, R);
       if (c.Ci16) store_packed(c.Ci16, s, 18 * b, R);
@@ -293,7 +239,7 @@ __global__ __launch_bounds__(128) void k_clover(const CloverLaunch c) {
           for (int k = 0; k < 6; ++k) v = cadd(v, cmul(B[i][k], B[k][j]));
           Q[i][j] = v;
         }
-      if (!herm6_inverse(Q, Qi)) atomicOr(c.err_flag, 1);
+      if (blk6::herm_inverse(Q, Qi) == blk6::INV_SINGULAR) atomicOr(c.err_flag, 1);
       store_packed(c.Ci64, s, 18 * b, Qi);
       if (c.Ci32) store_packed(c.Ci32, s, 18 * b, Qi);
       if (c.Ci16) store_packed(c.Ci16, s, 18 * b, Qi);
