@@ -14,10 +14,16 @@
 // number times the unit roundoff of the inner precision approaches one
 // (e.g. near-zero modes) makes little or no progress on the true residual
 // however long it runs.  Every reliable update compares the true residual
-// with the best one so far; after stall_max consecutive updates without
-// halving it the rhs is marked CG_STALLED and the host continues it in FP64
-// from the current solution.  Healthy solves gain about a factor ten per
-// update (the update is triggered by a tenfold drop of the recursive |r|).
+// with the best one so far; consecutive updates that do not halve it add to
+// a count, and when the count reaches stall_max the rhs is marked CG_STALLED
+// and the host continues it in FP64 from the current solution.  An update
+// requested because the recursive |r| fell tenfold (or reached the inner
+// target) and yet bought less than a halving of the true residual is the
+// signature of a recursion that no longer tracks the true residual: it adds
+// kDropWeight, so two in a row stall the rhs.  An update requested by the
+// iteration count alone adds one: slow but real progress of an
+// ill-conditioned system is not a stall, and eight such updates without a
+// halving are needed.  Healthy solves gain about a factor ten per update.
 #include <algorithm>
 
 #include "lqcd_kernels.h"
@@ -26,6 +32,7 @@ namespace lqcd {
 
 constexpr int kB = 256;
 constexpr double kGain2 = 0.25;  // required gain on |eta - Dw x|^2 (halving the residual)
+constexpr int kDropWeight = 4;   // stall count of a drop-requested update without gain
 
 __device__ inline double bsum(double v, double* sh) {
 #pragma unroll
@@ -82,7 +89,7 @@ __global__ void k_cg_setup(CGState* s, const double* b2, const double* eta2, CGS
   c.best_rho2 = 1.0;
   c.stall_max = cfg.stall_max;
   c.fp64_from = 0;
-  c.pad_ = 0;
+  c.ru_drop = 0;
   const bool zero = !(b > 0.0) || !(eta2[r] > 0.0);
   c.done = zero ? 1 : 0;
   c.status = zero ? CG_CONVERGED : CG_RUNNING;
@@ -116,9 +123,12 @@ __device__ inline void beta_step(CGState& c, double v) {
   }
   const bool hit = v <= c.target2;
   const bool due = c.ru_every > 0 && c.iters - c.last_ru >= c.ru_every;
-  if (hit || due || v < c.delta2 * c.rr_max) {
+  const bool drop = v < c.delta2 * c.rr_max;
+  if (hit || due || drop) {
+    if (c.skip_ru) c.ru_drop = 0;  // a new request
     c.skip_ru = 0;
     if (hit) c.inner_hit = 1;
+    if (hit || drop) c.ru_drop = 1;
   }
   c.beta = (c.rr_prev > 0.0) ? v / c.rr_prev : 0.0;
   c.rr = v;
@@ -291,7 +301,7 @@ __global__ void k_ru_finish(CGState* s, const double* part_res, int n_res, const
       c.best_rho2 = c.rho2;
       c.no_gain = 0;
     } else {
-      c.no_gain += 1;
+      c.no_gain += c.ru_drop ? kDropWeight : 1;
     }
     if (c.no_gain >= c.stall_max) {
       c.done = 1;
@@ -326,6 +336,7 @@ __global__ void k_cg_escalate(CGState* s, int n) {
   c.skip_ru = 0;  // the first FP64 step recomputes r from x
   c.stall_max = 0;
   c.no_gain = 0;
+  c.ru_drop = 0;
   c.delta2 = 0.0;
   c.ru_every = 0;
   c.inner_hit = 0;

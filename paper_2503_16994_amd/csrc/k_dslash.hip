@@ -224,9 +224,9 @@ __device__ inline void load_block(const SG* C, int blk, int s, bool cached, cpx<
 //            Lz % 16 == 0).
 // Tile-inner orders read each link once for all tiles but need a reuse window
 // holding all rhs; tile-outer orders read the links once per tile and keep
-// the reuse window of a single tile.  A launch over both parities is two
-// halves of the grid, each mapped like a one-parity launch (nb and nbs per
-// half).
+// the reuse window of a single tile.  A launch over both parities maps each parity like a one-parity launch (nb
+// and nbs per parity); the parities alternate every round of eight
+// workgroups (see hop_thread).
 __device__ inline void block_order(const HopLaunch& a, int b, int nb, int nbs, int ntiles, int& sb, int& tile) {
   if (a.order == 0) {
     sb = b % nbs;
@@ -311,11 +311,24 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
   ts.c0 = 6 * wv;
   const KGeom& g = a.g;
   int tile, p = a.p_out, b = blockIdx.x, nb = gridDim.x, nbs = a.nbs;
-  if (a.both) {  // parity 0 in the first half of the grid, parity 1 in the second
+  if (a.both) {
+    // Both parities: with a whole number of XCD rounds per parity, the
+    // parities alternate every XCD round (workgroups 8j .. 8j+7 run parity
+    // j mod 2, one per XCD), so that each XCD handles parity-0 and parity-1
+    // blocks of the same sites together and the links that a parity-1 site
+    // reads backward (stored with its parity-0 neighbour) were just read
+    // forward by the parity-0 block, and are L2 hits; otherwise parity 0
+    // takes the first half of the grid and parity 1 the second.
     nb >>= 1;
     nbs >>= 1;
-    p = (b >= nb) ? 1 : 0;
-    b -= p * nb;
+    if ((nb & 7) == 0) {
+      const int j = b >> 3;
+      p = j & 1;
+      b = ((j >> 1) << 3) | (b & 7);
+    } else {
+      p = (b >= nb) ? 1 : 0;
+      b -= p * nb;
+    }
   }
   int bx;  // site block within the parity
   block_order(a, b, nb, nbs, a.nrhs / (NR * RL), bx, tile);

@@ -658,6 +658,9 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
   lqcd_tuning best_cfg = saved;
   OpCtx c{u, w, prec, nrhs, st, d->mu};
   hipError_t err = hipSuccess;
+  // LQCD_TUNE_LOG=1: every candidate's time on stderr (diagnostics)
+  const char* log_env = getenv("LQCD_TUNE_LOG");
+  const bool log_trials = log_env && log_env[0] == '1';
   // times the workspace's current tuning; keeps it if it is the fastest so far
   auto trial = [&]() {
     auto once = [&]() -> hipError_t {
@@ -677,6 +680,11 @@ extern "C" int lqcd_autotune(const lqcd_gauge_t* u, const lqcd_dirac* d, int pre
       float ms = 0.f;
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
       if (err == hipSuccess && 1e3 * ms < us) us = 1e3 * ms;
+    }
+    if (err == hipSuccess && log_trials) {
+      const lqcd_tuning& t = w->tune[prec];
+      fprintf(stderr, "lqcd_autotune V=%lld prec=%d nrhs=%d nr_tile=%d rhs_lanes=%d order=%d flags=%d us=%.2f\n",
+              (long long)w->g->V, prec, nrhs, t.nr_tile, t.rhs_lanes, t.block_order, t.flags, us);
     }
     if (err == hipSuccess && us < best_t) {
       best_t = us;

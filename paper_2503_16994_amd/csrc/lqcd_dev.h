@@ -79,7 +79,10 @@ struct StoreTraits<float2> {
   }
 };
 
-// float -> bfloat16 with round-to-nearest-even; NaN stays NaN (quiet bit set)
+// float -> bfloat16 with round-to-nearest-even on the bits; NaN stays NaN
+// (quiet bit set).  Used where the source is an FP64 value: its FP32
+// rounding comes first, and bit arithmetic keeps the compiler from folding
+// the two roundings into one FP64 -> BF16 conversion.
 __device__ __host__ inline uint32_t f32_to_bf16_rne(float f) {
   union {
     float f;
@@ -90,6 +93,14 @@ __device__ __host__ inline uint32_t f32_to_bf16_rne(float f) {
   if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
+}
+
+// two floats -> packed bfloat16 pair (re low, im high) by the hardware
+// conversion (v_cvt_pk_bf16_f32), round to nearest even; a NaN stays a NaN
+__device__ inline uint32_t pack_bf16x2(float re, float im) {
+  const __bf16 lo = (__bf16)re, hi = (__bf16)im;
+  return (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+         ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
 }
 
 __device__ __host__ inline float bf16_to_f32(uint32_t h) {
@@ -108,11 +119,10 @@ struct StoreTraits<bf16x2> {
     uint32_t v = p->v;
     return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
   }
-  __device__ static inline void store(bf16x2* p, cpx<float> c) {
-    p->v = f32_to_bf16_rne(c.re) | (f32_to_bf16_rne(c.im) << 16);
-  }
+  __device__ static inline void store(bf16x2* p, cpx<float> c) { p->v = pack_bf16x2(c.re, c.im); }
+  // FP64 -> FP32 -> BF16, each step round-to-nearest-even
   __device__ static inline void store(bf16x2* p, cpx<double> c) {
-    store(p, cpx<float>{(float)c.re, (float)c.im});
+    p->v = f32_to_bf16_rne((float)c.re) | (f32_to_bf16_rne((float)c.im) << 16);
   }
 };
 
@@ -153,8 +163,9 @@ __device__ inline void st_nt(float2* p, cpx<A> c) {
 }
 template <typename A>
 __device__ inline void st_nt(bf16x2* p, cpx<A> c) {
-  const uint32_t v = f32_to_bf16_rne((float)c.re) | (f32_to_bf16_rne((float)c.im) << 16);
-  __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(p));
+  bf16x2 t;
+  StoreTraits<bf16x2>::store(&t, c);  // the rounding of an ordinary store
+  __builtin_nontemporal_store(t.v, reinterpret_cast<uint32_t*>(p));
 }
 
 // Block index remap for the 8 XCDs of the MI355X.  Workgroups are handed to
@@ -195,6 +206,25 @@ template <typename A>
 __device__ inline cpx<A> csub_i(cpx<A> a, cpx<A> b) { return {a.re + b.im, a.im - b.re}; }
 template <typename A>
 __device__ inline cpx<A> cscale(A s, cpx<A> a) { return {s * a.re, s * a.im}; }
+// acc + a b and acc + conj(a) b with each of the four real products fused
+// into the running sum (four FMAs per complex multiply-accumulate; the
+// expression acc + (a b) would cost a multiply, an FMA and an add per part)
+template <typename A>
+__device__ inline cpx<A> cmac(cpx<A> acc, cpx<A> a, cpx<A> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+template <typename A>
+__device__ inline cpx<A> cmacc(cpx<A> acc, cpx<A> a, cpx<A> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
 
 // Third row of an SU(3) matrix (row major, m[3 a + b]) from its first two.
 // For a unitary matrix of determinant one the inverse is both the adjoint
@@ -202,9 +232,9 @@ __device__ inline cpx<A> cscale(A s, cpx<A> a) { return {s * a.re, s * a.im}; }
 // cofactor: row 2 = conj(row 0 x row 1).
 template <typename A>
 __device__ inline void su3_third_row(cpx<A> (&m)[9]) {
-  const cpx<A> c0 = csub(cmul(m[1], m[5]), cmul(m[2], m[4]));
-  const cpx<A> c1 = csub(cmul(m[2], m[3]), cmul(m[0], m[5]));
-  const cpx<A> c2 = csub(cmul(m[0], m[4]), cmul(m[1], m[3]));
+  const cpx<A> c0 = cmac(cmul(m[1], m[5]), cpx<A>{-m[2].re, -m[2].im}, m[4]);
+  const cpx<A> c1 = cmac(cmul(m[2], m[3]), cpx<A>{-m[0].re, -m[0].im}, m[5]);
+  const cpx<A> c2 = cmac(cmul(m[0], m[4]), cpx<A>{-m[1].re, -m[1].im}, m[3]);
   m[6] = {c0.re, -c0.im};
   m[7] = {c1.re, -c1.im};
   m[8] = {c2.re, -c2.im};
@@ -339,8 +369,8 @@ __device__ inline void su3_mul(const cpx<A> (&U)[9], const cpx<A> (&h)[2][3], cp
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cpx<A> v = cmul(U[3 * a + 0], h[s][0]);
-      v = cadd(v, cmul(U[3 * a + 1], h[s][1]));
-      v = cadd(v, cmul(U[3 * a + 2], h[s][2]));
+      v = cmac(v, U[3 * a + 1], h[s][1]);
+      v = cmac(v, U[3 * a + 2], h[s][2]);
       w[s][a] = v;
     }
 }
@@ -354,8 +384,8 @@ __device__ inline void su3_dag_mul(const cpx<A> (&U)[9], const cpx<A> (&h)[2][3]
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cpx<A> v = cmulc(U[0 * 3 + a], h[s][0]);
-      v = cadd(v, cmulc(U[1 * 3 + a], h[s][1]));
-      v = cadd(v, cmulc(U[2 * 3 + a], h[s][2]));
+      v = cmacc(v, U[1 * 3 + a], h[s][1]);
+      v = cmacc(v, U[2 * 3 + a], h[s][2]);
       w[s][a] = v;
     }
 }
@@ -373,8 +403,8 @@ __device__ inline void herm6_mul(const cpx<A> (&m)[18], const cpx<A> (&v)[6], cp
     cpx<A> acc = cscale(d[i], v[i]);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      if (j < i) acc = cadd(acc, cmul(m[tri_index(i, j)], v[j]));
-      if (j > i) acc = cadd(acc, cmulc(m[tri_index(j, i)], v[j]));
+      if (j < i) acc = cmac(acc, m[tri_index(i, j)], v[j]);
+      if (j > i) acc = cmacc(acc, m[tri_index(j, i)], v[j]);
     }
     o[i] = acc;
   }

@@ -52,7 +52,7 @@ struct HopLaunch {
   bool both;
   long par_stride;
   long cpre_par;
-  // tuning: block order (0..4, see block_order in k_dslash.hip) and the
+  // tuning: block order (0..6, see block_order in k_dslash.hip) and the
   // number of lanes that share a site and split its rhs (1, 2, 4)
   int order;
   int rhs_lanes;
@@ -171,10 +171,11 @@ struct CGState {
   int last_ru;     // iteration of the last reliable update
   double target0;    // initial inner target
   double best_rho2;  // smallest true residual^2 (relative) at a reliable update
-  int no_gain;       // consecutive reliable updates that did not halve best_rho2
-  int stall_max;     // CG_STALLED after this many (0: never)
+  int no_gain;       // weighted count of consecutive reliable updates that did not halve best_rho2
+  int stall_max;     // CG_STALLED when no_gain reaches this (0: never)
   int fp64_from;     // iteration at which the rhs continued in FP64 (0: never)
-  int pad_;
+  int ru_drop;       // the pending reliable update was requested by a drop of |r|^2
+                     // (tenfold, or the inner target), not by the iteration count
 };
 
 struct CGSetup {

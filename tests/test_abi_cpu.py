@@ -87,10 +87,10 @@ def test_geometry_sizes():
     assert lib.lqcd_gauge_bytes(h, lqcd.PM_F64) >= 2 * 36 * 320 * 16
     # two rows per link: 24 instead of 36 complex per site and parity, plus
     # the 256-byte flag of the SU(3) check
-    full = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_BF16)
-    two = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_BF16 | lqcd.PM_TWO_ROW)
-    assert two == 2 * 24 * 320 * 16 + 2 * 24 * 320 * 4 + 256
-    assert full == 2 * 36 * 320 * 16 + 2 * 36 * 320 * 4
+    full = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16)
+    two = lib.lqcd_gauge_bytes(h, lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16 | lqcd.PM_TWO_ROW)
+    assert two == 2 * 24 * 320 * 16 + 2 * 24 * 320 * 8 + 2 * 24 * 320 * 4 + 256
+    assert full == 2 * 36 * 320 * 16 + 2 * 36 * 320 * 8 + 2 * 36 * 320 * 4
     lib.lqcd_geom_free(h)
 
 
