@@ -16,9 +16,11 @@ before it.  Beside it, the same 12 sources solved one at a time by the FP64
 CG (the metric's "solves/s mixed vs FP64") and with FP32 inner precision.
 
 The JSON line (stdout) also carries
-* "roofline": the dominant kernel of the step (algorithmic bytes per launch /
-  average launch time, launches replayed from one graph, HIP events on its
-  stream), and the FP64 one-rhs hop of the baseline at the same size;
+* "roofline": the dominant kernel of the step, the BF16 12-rhs e->o hop, bound
+  by FP32 vector arithmetic (algorithmic flops per launch / average launch
+  time, launches replayed from one graph, HIP events on its stream, against
+  the FP32 vector peak without dual issue), with its HBM rate beside it; the
+  FP64 one-rhs hop of the baseline at the same size (HBM bound);
 * "c2": the 16^3x32 propagator (kappa 0.1345), FP64 one source at a time and
   12 rhs per solve in FP64/FP32/BF16 inner precision;
 * "mixed_c4": the 24^3x48 Schroedinger-functional propagator (kappa 0.134,
@@ -74,6 +76,15 @@ def hop_reals(op, nrhs=1, two_row=True, tm=False):
     return u + 72 + 48 * nrhs  # full Dw: U + A + psi + out
 
 
+# Algorithmic flops per output site and rhs of one hop launch (the standard
+# Wilson-clover count): eight hops of 168 flops (spin projection 12, SU(3)
+# times a two-spinor 132, reconstruction 24) less the 24 of the first
+# accumulation = 1320; the -1/2 scale 24; two Hermitian 6x6 blocks times a
+# 6-vector 2 x 252 = 504; o->e adds the self term (24 more).
+FLOPS_PER_SITE_RHS = {"hop_eo": 1320 + 24 + 504, "hop_oe": 1320 + 24 + 504 + 24}
+# FP32 vector peak without packed (dual) FP32 issue, which this build disables
+# for correctness: 256 CUs x 64 FMA lanes per clock x 2 flop x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # 78.6
 BYTES_PER_REAL = {0: 8, 1: 4, 2: 2}
 PREC_NAME = {0: "f64", 1: "f32", 2: "bf16"}
 # hop tuning of the 16^3x32 FP64 one-at-a-time solves (nr_tile, block_order,
@@ -181,6 +192,25 @@ def hop_roofline(g, lat_, ws, d, op_name, prec, nrhs, stream, launches):
             "links": "two rows per link" if tr else "full"}
 
 
+def alu_roofline(h, op_name, nrhs, lat_):
+    """Roofline entry of a hop launch bound by FP32 vector arithmetic (the
+    reduced-precision multi-rhs launches: rocprofv3 counts their VALU
+    instructions at ~90% of the issue slots of the launch): algorithmic
+    flops per launch / average launch time against the FP32 vector peak; the
+    HBM figures of the same launch are kept beside it."""
+    flops = FLOPS_PER_SITE_RHS[op_name] * (lat_.volume // 2) * nrhs
+    achieved = flops / (h["avg_launch_us"] * 1e-6) / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+           "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": h["traffic"],
+           "flops_per_launch": flops, "hbm_achieved_GBps": h["achieved"], "hbm_frac": h["frac"],
+           "peak_note": "FP32 FMA without packed-FP32 dual issue (disabled in this build): "
+                        "256 CUs x 64 lanes x 2 flop x 2.4 GHz; the published 157.3 TFLOP/s counts dual issue"}
+    for k in ("traffic_vs_alg", "kernel", "lattice", "avg_launch_us", "alg_bytes_per_launch", "tuning", "links"):
+        if k in h:
+            out[k] = h[k]
+    return out
+
+
 def time_launches(fn, reps, stream):
     import torch
     for _ in range(3):
@@ -284,18 +314,17 @@ def main():
     ws12 = lqcd.Workspace(lat, pm, 12)
 
     def tune_mixed(ws, g, d, ip, nrhs):
-        """the inner precision's tuning from the committed table, else
-        autotuned; the FP64 hops of the reliable updates run one rhs per
-        thread with the direction split"""
-        tune = lqcd.tune_cache_find(g, ip, nrhs)
-        if tune is None:
-            tune, _ = lqcd.autotune(g, d, ip, nrhs, ws, stream=stream)
-        else:
-            lqcd.set_tuning(ws, ip, **tune)
-        if ip != lqcd.F64:
-            t64 = lqcd.get_tuning(ws, lqcd.F64)
-            t64["dir_split"] = True
-            lqcd.set_tuning(ws, lqcd.F64, **t64)
+        """the tuning of the inner precision and of FP64 (the hops of the
+        reliable updates) for nrhs rhs: from the committed table, else
+        autotuned"""
+        for prec in (ip, lqcd.F64):
+            t = lqcd.tune_cache_find(g, prec, nrhs)
+            if t is None:
+                t, _ = lqcd.autotune(g, d, prec, nrhs, ws, stream=stream)
+            else:
+                lqcd.set_tuning(ws, prec, **t)
+            if prec == ip:
+                tune = t
         return tune
 
     def solve12(ip, ws):
@@ -329,10 +358,11 @@ def main():
     log(f"32^3x64 12-rhs FP32 inner: {step_f32}")
     # roofline of the step's dominant kernel (the BF16 12-rhs e->o hop, two
     # launches per iteration) in the step's tuning
-    roofline = hop_roofline(g3, lat, ws12, d3, "hop_eo", lqcd.BF16, 12, stream, 20)
-    roofline["o_to_e_same_tuning"] = {k: v for k, v in hop_roofline(g3, lat, ws12, d3, "hop_oe", lqcd.BF16, 12,
-                                                                     stream, 20).items()
-                                      if k in ("achieved", "frac", "avg_launch_us", "traffic", "traffic_vs_alg")}
+    roofline = alu_roofline(hop_roofline(g3, lat, ws12, d3, "hop_eo", lqcd.BF16, 12, stream, 20), "hop_eo", 12, lat)
+    roofline["o_to_e_same_tuning"] = {
+        k: v for k, v in alu_roofline(hop_roofline(g3, lat, ws12, d3, "hop_oe", lqcd.BF16, 12, stream, 20),
+                                      "hop_oe", 12, lat).items()
+        if k in ("achieved", "frac", "avg_launch_us", "traffic", "traffic_vs_alg", "hbm_achieved_GBps", "hbm_frac")}
     del ws12
     torch.cuda.empty_cache()
     ws1 = lqcd.Workspace(lat, pm, 1)
@@ -410,17 +440,15 @@ def main():
 
 def mixed_leg(stream, g, lat_, ws, etas, kappa, csw, fp64_sps, steps, warmup, tag, precs=("f64", "f32", "bf16")):
     """12 rhs in one solve per inner precision (autotuned kernels; the FP64
-    hops of the reliable updates with the direction split), vs fp64_sps."""
+    hops of the reliable updates in the 12-rhs FP64 tuning), vs fp64_sps."""
     from paper_2503_16994_amd import lqcd
     res = {}
     pmap = {"f64": lqcd.F64, "f32": lqcd.F32, "bf16": lqcd.BF16}
     for name in precs:
         ip = pmap[name]
+        # the FP64 tuning of the workspace stays the 12-rhs one of the f64
+        # leg: the reliable updates of the mixed solves run in it
         tune, _ = lqcd.autotune(g, lqcd.dirac(kappa, csw), ip, 12, ws, stream=stream)
-        if ip != lqcd.F64:
-            t64 = lqcd.get_tuning(ws, lqcd.F64)
-            t64["dir_split"] = True
-            lqcd.set_tuning(ws, lqcd.F64, **t64)
 
         def mstep():
             return lqcd.solve(g, etas, kappa, csw, tol=TOL, solver=lqcd.SOLVER_CG_EO, inner_prec=ip,
@@ -753,8 +781,8 @@ def profile_kernels(stream):
     1 GiB fill and a 1 GiB read-only sum, then, at 32^3x64 on two-row links in
     the step's tunings (the committed tuning table), 20 launches of each hop
     kernel of the step and its baseline: BF16 and FP32 with 12 rhs, FP64 with
-    one rhs (e->o, then o->e); then 10 meson contractions of a random
-    12-column field."""
+    one rhs (e->o, then o->e, then the full-lattice Dw); then 10 meson
+    contractions of a random 12-column field."""
     import torch
 
     from paper_2503_16994_amd import inputs, lqcd
@@ -785,7 +813,10 @@ def profile_kernels(stream):
         ws = ws12 if nrhs == 12 else ws1
         lqcd.set_tuning(ws, prec, **t)
         x, y = internal_vectors(lat, prec, nrhs)
-        for op in (lqcd.OP_HOP_EO, lqcd.OP_HOP_OE):
+        # the two hops, then (FP64, one rhs) the full-lattice Dw of the
+        # residual checks
+        ops = (lqcd.OP_HOP_EO, lqcd.OP_HOP_OE) + ((lqcd.OP_DW,) if prec == lqcd.F64 else ())
+        for op in ops:
             for _ in range(20):
                 lqcd.dw_apply_internal(g, d, x, y, op, prec, nrhs, ws, stream=stream)
         torch.cuda.synchronize()

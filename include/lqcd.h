@@ -426,14 +426,16 @@ int lqcd_server_create(void *arena, size_t arena_bytes, int max_streams, int que
 int lqcd_server_add_gauge(lqcd_server_t *s, const lqcd_geom_desc *desc, const void *U_host,
                           int pmask, int *gauge_id);
 /* Autotunes the hop kernels of gauge field gauge_id for requests of
- * precision inner_prec with nrhs right-hand sides, on an otherwise idle GPU
- * (a workspace borrowed from the arena, the server's own stream; no request
- * is admitted meanwhile), and stores the result in the tuning cache.
- * Requests never tune: each takes the cached tuning of its lattice, inner
- * precision and rhs count (mu != 0 and the split bit as keys; the server
- * never sets the split), else the default, and tunings never change a result.
- * Does nothing if an entry exists.  EBUSY while a request is queued or
- * running; ENOMEM if the arena has no room for the workspace. */
+ * precision inner_prec with nrhs right-hand sides (for a low-precision
+ * inner_prec and nrhs > 1 also the FP64 kernels of their reliable updates),
+ * on an otherwise idle GPU (a workspace borrowed from the arena, the server's
+ * own stream; no request is admitted meanwhile), and stores the results in
+ * the tuning cache.  Requests never tune: each takes the cached tunings of
+ * its lattice, precisions and rhs count (mu != 0 and the split bit as keys;
+ * the server never sets the split), else the default, and tunings never
+ * change a result.  Does nothing if the entries exist.  EBUSY while a
+ * request is queued or running; ENOMEM if the arena has no room for the
+ * workspace. */
 int lqcd_server_warmup(lqcd_server_t *s, int gauge_id, int inner_prec, int nrhs);
 /* Device bytes one request with these parameters holds while it runs. */
 size_t lqcd_request_bytes(lqcd_server_t *s, int gauge_id, const lqcd_solve_params *p);

@@ -193,6 +193,9 @@ void lqcd_server::run(Request* r, const GaugeEntry& g, int idx) {
     lqcd_tuning t;
     if (lqcd_tune_cache_find(g.gauge, p.inner_prec, p.nrhs, p.d.mu != 0.0, 0, &t) == LQCD_OK)
       lqcd_ws_set_tuning(ws, p.inner_prec, &t);
+    // the FP64 tuning of the reliable updates of a mixed solve
+    if (p.inner_prec != LQCD_F64 && lqcd_tune_cache_find(g.gauge, LQCD_F64, p.nrhs, p.d.mu != 0.0, 0, &t) == LQCD_OK)
+      lqcd_ws_set_tuning(ws, LQCD_F64, &t);
     hipError_t e = hipMemcpyAsync(eta_dev, r->eta, canon, hipMemcpyHostToDevice, st);
     // an initial guess travels in the solution buffer (lqcd_solve reads x0
     // before it writes psi)
@@ -344,6 +347,7 @@ extern "C" int lqcd_server_warmup(lqcd_server_t* s, int gauge_id, int inner_prec
     return fail(LQCD_EINVAL, "lqcd_server_warmup: bad precision or nrhs");
   GaugeEntry g;
   size_t off = 0, bytes = 0;
+  bool need_inner = false, need64 = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (gauge_id < 0 || gauge_id >= (int)s->gauges.size())
@@ -356,7 +360,11 @@ extern "C" int lqcd_server_warmup(lqcd_server_t* s, int gauge_id, int inner_prec
       return fail(LQCD_EBUSY, "lqcd_server_warmup: requests are queued or running");
     if (s->sim) return LQCD_OK;
     lqcd_tuning t;
-    if (lqcd_tune_cache_find(g.gauge, inner_prec, nrhs, 0, 0, &t) == LQCD_OK) return LQCD_OK;
+    need_inner = lqcd_tune_cache_find(g.gauge, inner_prec, nrhs, 0, 0, &t) != LQCD_OK;
+    // the FP64 hops of the reliable updates of a multi-rhs mixed solve run in
+    // the FP64 tuning of the same rhs count
+    need64 = inner_prec != LQCD_F64 && nrhs > 1 && lqcd_tune_cache_find(g.gauge, LQCD_F64, nrhs, 0, 0, &t) != LQCD_OK;
+    if (!need_inner && !need64) return LQCD_OK;
     const int pm = LQCD_PM_F64 | (inner_prec == LQCD_F32 ? LQCD_PM_F32 : 0) |
                    (inner_prec == LQCD_BF16 ? LQCD_PM_BF16 : 0);
     bytes = lqcd_ws_bytes(g.geom, pm, nrhs);
@@ -371,7 +379,9 @@ extern "C" int lqcd_server_warmup(lqcd_server_t* s, int gauge_id, int inner_prec
   if (rc == LQCD_OK) {
     // any Dirac parameters: the clover values do not change kernel timings
     const lqcd_dirac d{0.13, 1.9, 1.0, 0.0};
-    rc = lqcd_autotune(g.gauge, &d, inner_prec, nrhs, ws, s->import_stream, nullptr, nullptr);
+    if (need_inner) rc = lqcd_autotune(g.gauge, &d, inner_prec, nrhs, ws, s->import_stream, nullptr, nullptr);
+    if (rc == LQCD_OK && need64)
+      rc = lqcd_autotune(g.gauge, &d, LQCD_F64, nrhs, ws, s->import_stream, nullptr, nullptr);
     const hipError_t e = hipStreamSynchronize(s->import_stream);
     if (rc == LQCD_OK && e != hipSuccess) rc = hip_status(e, "lqcd_server_warmup");
     lqcd_ws_free(ws);

@@ -327,10 +327,13 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   CGState* cg = m.cg;
   const int* done = &cg[0].done;
   const int* skip_ru = &cg[0].skip_ru;
-  // partials per rhs of an FP64 single-tile hop launch (setup and reliable updates)
+  // partials per rhs of an FP64 single-tile hop launch (setup, and the
+  // reliable updates of FP64 phases), and of an FP64 launch in the
+  // workspace's tuning (the reliable updates of low-precision phases)
   HopLaunch h1 = mk(c, P_F64);
   single_tile(h1);
   const int nb_hop = hop_nparts(h1);
+  const int nb_hop_tuned = hop_nparts(mk(c, P_F64));
 
   LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
   if (x0)
@@ -402,17 +405,26 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   LQCD_HIP(launch_cg_setup(cg, scal, scal + N, cfg, st));
 
   // ---- reliable update group (skips rhs without a pending request) ---------
+  // The FP64 hops skip whole rhs tiles whose rhs have no pending request.  In
+  // an FP64 phase the update writes the recursion's own residual R, so every
+  // rhs is its own tile; in a low-precision phase the hops write only FP64
+  // scratch (TMP, Q, AP) that the other rhs do not use (the fold, the
+  // residual and the copy into the recursion skip them), so the hops run in
+  // the workspace's FP64 tuning: with the rhs of a propagator requesting
+  // their updates together, one multi-rhs launch instead of one per rhs.
   auto reliable_update = [&]() -> hipError_t {
     hipError_t e;
     if (eo) {
+      const int ru_tile = lo ? 0 : 1;
+      const int nb_ru = lo ? nb_hop_tuned : nb_hop;
       if (lo && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
-      if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, 1))) return e;
-      if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, 1))) return e;
+      if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, ru_tile))) return e;
+      if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, ru_tile))) return e;
       if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, N, cg, parts2, st))) return e;
-      if ((e = hop_eo(dg(c), P_F64, AP, odd_part(TMP, V2), skip_ru, 1))) return e;
-      if ((e = hop_oe(dg(c), P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, 1))) return e;
+      if ((e = hop_eo(dg(c), P_F64, AP, odd_part(TMP, V2), skip_ru, ru_tile))) return e;
+      if ((e = hop_oe(dg(c), P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, ru_tile))) return e;
       if (lo && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
-      return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_hop, N, st);
+      return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_ru, N, st);
     }
     if ((e = dw_full(c, m.X, m.TMP, false, nullptr, skip_ru))) return e;
     if ((e = launch_ru_sub(m.E, m.TMP, m.AP, 24 * V2, FRS, N, cg, parts2, st))) return e;
