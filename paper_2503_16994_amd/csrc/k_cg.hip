@@ -178,18 +178,17 @@ __global__ void k_cg_xr(SX* x, S* r, const S* __restrict__ p, const S* __restric
 }
 
 // p = r + beta p ; optional low-precision copy of p
-template <typename S, typename SL>
-__global__ void k_cg_p(S* p, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
+template <typename S, typename SP, typename SL>
+__global__ void k_cg_p(SP* p, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
   const int q = blockIdx.y;
   if (cs[q].done) return;
   using A = typename StoreTraits<S>::acc;
   const A beta = (A)cs[q].beta;
   const size_t o = (size_t)q * rs;
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
-    auto pv = ld(p + o + i);
-    auto rv = ld(r + o + i);
-    pv.re = rv.re + beta * pv.re;
-    pv.im = rv.im + beta * pv.im;
+    const auto p0 = ld(p + o + i);
+    const auto rv = ld(r + o + i);
+    const cpx<A> pv = {rv.re + beta * (A)p0.re, rv.im + beta * (A)p0.im};
     st(p + o + i, pv);
     if (plo) st(plo + o + i, pv);
   }
@@ -201,8 +200,8 @@ __global__ void k_cg_p(S* p, const S* __restrict__ r, long n, long rs, const CGS
 // A rhs that workgroup 0 marks done meanwhile may see p updated by only some
 // workgroups, which is harmless: done is final here (only the reliable
 // update's finish kernel sets the resumable CG_STALLED).
-template <typename S, typename SL>
-__global__ void k_cg_beta_p(S* p, const S* __restrict__ r, long n, long rs, CGState* cs, SL* plo,
+template <typename S, typename SP, typename SL>
+__global__ void k_cg_beta_p(SP* p, const S* __restrict__ r, long n, long rs, CGState* cs, SL* plo,
                             const double* partials, int nparts) {
   __shared__ double sh[4];
   const int q = blockIdx.y;
@@ -216,10 +215,9 @@ __global__ void k_cg_beta_p(S* p, const S* __restrict__ r, long n, long rs, CGSt
   const A beta = (A)((rr0 > 0.0) ? v / rr0 : 0.0);
   const size_t o = (size_t)q * rs;
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
-    auto pv = ld(p + o + i);
-    auto rv = ld(r + o + i);
-    pv.re = rv.re + beta * pv.re;
-    pv.im = rv.im + beta * pv.im;
+    const auto p0 = ld(p + o + i);
+    const auto rv = ld(r + o + i);
+    const cpx<A> pv = {rv.re + beta * (A)p0.re, rv.im + beta * (A)p0.im};
     st(p + o + i, pv);
     if (plo) st(plo + o + i, pv);
   }
@@ -394,13 +392,16 @@ hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, co
 hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs, const CGState* s,
                        void* plo, int lo_prec, hipStream_t st) {
   dim3 grid(blas_nblocks(n), nrhs);
-  if (prec == P_F64)
-    k_cg_p<double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
-                                                  (double2*)nullptr);
-  else if (prec == P_F32 && (plo == nullptr || lo_prec == P_F32))
-    k_cg_p<float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo);
-  else if (prec == P_F32 && lo_prec == P_BF16)
-    k_cg_p<float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo);
+  if (prec == P_F64 && p)
+    k_cg_p<double2, double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
+                                                           (double2*)nullptr);
+  else if (prec == P_F32 && p && (plo == nullptr || lo_prec == P_F32))
+    k_cg_p<float2, float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo);
+  else if (prec == P_F32 && p && plo && lo_prec == P_BF16)
+    k_cg_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo);
+  else if (prec == P_F32 && !p && plo && lo_prec == P_BF16)  // the direction lives in BF16 only
+    k_cg_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((bf16x2*)plo, (const float2*)r, n, rs, s,
+                                                        (bf16x2*)nullptr);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -414,15 +415,18 @@ hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, i
   const int nb = blas_nblocks(n);
   const int nbx = std::min(nb, std::max(256, nb / nrhs));
   dim3 grid(nbx, nrhs);
-  if (prec == P_F64)
-    k_cg_beta_p<double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
-                                                       (double2*)nullptr, partials, nparts);
-  else if (prec == P_F32 && (plo == nullptr || lo_prec == P_F32))
-    k_cg_beta_p<float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo,
-                                                     partials, nparts);
-  else if (prec == P_F32 && lo_prec == P_BF16)
-    k_cg_beta_p<float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo,
-                                                     partials, nparts);
+  if (prec == P_F64 && p)
+    k_cg_beta_p<double2, double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
+                                                                (double2*)nullptr, partials, nparts);
+  else if (prec == P_F32 && p && (plo == nullptr || lo_prec == P_F32))
+    k_cg_beta_p<float2, float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s,
+                                                             (float2*)plo, partials, nparts);
+  else if (prec == P_F32 && p && plo && lo_prec == P_BF16)
+    k_cg_beta_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s,
+                                                             (bf16x2*)plo, partials, nparts);
+  else if (prec == P_F32 && !p && plo && lo_prec == P_BF16)  // the direction lives in BF16 only
+    k_cg_beta_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((bf16x2*)plo, (const float2*)r, n, rs, s,
+                                                             (bf16x2*)nullptr, partials, nparts);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

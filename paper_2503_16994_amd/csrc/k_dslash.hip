@@ -610,7 +610,8 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
 
 // The last hop of a CG iteration fused with the vector update: with
 // Ap = g5 (A_ee q + 1/2 H t) computed in registers, every rhs that is not done
-// gets x += alpha p, r -= alpha Ap (x, r, p of type SV at this site) and the
+// gets x += alpha p, r -= alpha Ap (x, r of type SV, p of the operator's
+// input type SI: the very vector the operator was applied to) and the
 // per-block |r|^2 partial.  Ap is never stored.
 template <typename SG, typename SI, typename SV, int NR, int RL, bool SPLIT, bool TM>
 __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
@@ -624,7 +625,7 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   if (!hop_thread<SG, SI, PRE_CLOV, POST_NONE, true, NR, RL, SPLIT, TM>(a, ts, v, xch)) return;
   SV* xb = static_cast<SV*>(a.xr_x);
   SV* rb = static_cast<SV*>(a.xr_r);
-  const SV* pb = static_cast<const SV*>(a.xr_p);
+  const SI* pb = static_cast<const SI*>(a.xr_p);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int q = ts.rhs0 + r;

@@ -78,7 +78,7 @@ struct HopLaunch {
   void* xr_x;
   void* xr_r;
   const void* xr_p;
-  int xr_prec;   // precision of x, r, p
+  int xr_prec;   // precision of x and r (p has the operator's input precision)
   long xr_rs;    // rhs stride of r and p
   long xr_xrs;   // rhs stride of x
   const struct CGState* cg;
@@ -203,6 +203,8 @@ hipError_t launch_cg_beta(CGState* s, const double* partials, int nparts, int nr
 hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, const void* Ap,
                         int prec, long n, long rs, int nrhs, const CGState* s, double* partials,
                         hipStream_t st);
+// p = r + beta p, also written to p_lo (precision lo_prec) if given; with p
+// null the direction is kept in p_lo alone (BF16, r FP32): p_lo = r + beta p_lo
 hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs,
                        const CGState* s, void* p_lo, int lo_prec, hipStream_t st);
 // beta step and p update in one launch (nparts |r|^2 partials per rhs)

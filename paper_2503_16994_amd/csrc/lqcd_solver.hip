@@ -148,8 +148,8 @@ hipError_t hop_oe(const Ctl& c, int lprec, Vec z, Vec t_o, Vec out, bool g5, dou
 }
 
 // fused last hop + CG update: Ap = g5 (A_ee q_e + 1/2 H t_o) in registers,
-// x += alpha p, r -= alpha Ap, |r|^2 partials (x, r, p vectors of precision
-// vprec)
+// x += alpha p, r -= alpha Ap, |r|^2 partials (x and r in the recursion's
+// precision, p in the operator's input precision)
 hipError_t hop_oe_xr(const Ctl& c, int lprec, Vec q, Vec t_o, Vec x, Vec r, Vec p, double* partials,
                      const CGState* cg, const int* done) {
   HopLaunch h = mk(c, lprec);
@@ -389,8 +389,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   } else {
     LQCD_HIP(launch_fill_zero(m.xl, (size_t)N * HRS * 8, st));
     LQCD_HIP(launch_convert(m.R, P_F64, m.rl, P_F32, n_vec, FRS, HRS, N, st));
-    LQCD_HIP(launch_convert(m.rl, P_F32, m.pl, P_F32, n_vec, HRS, HRS, N, st));
     if (lo16) LQCD_HIP(launch_convert(m.rl, P_F32, m.pb, P_BF16, n_vec, HRS, HRS, N, st));
+    else LQCD_HIP(launch_convert(m.rl, P_F32, m.pl, P_F32, n_vec, HRS, HRS, N, st));
   }
   const int nr_tile = 0;  // 0: the workspace's tuned tile
 
@@ -438,8 +438,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   if (x0) {
     LQCD_HIP(launch_cg_force_ru(cg, N, st));
     LQCD_HIP(reliable_update());
-    void* plo = lo16 ? pin.p : nullptr;
-    LQCD_HIP(launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, lo16 ? P_BF16 : P_F32, st));
+    LQCD_HIP(launch_cg_p(lo16 ? nullptr : pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, lo16 ? pin.p : nullptr,
+                         lo16 ? P_BF16 : P_F32, st));
   }
 
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
@@ -455,7 +455,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
       if ((e = hop_eo(dg(c), lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
-      if ((e = hop_oe_xr(dg(c), lprec, qin, tin, xi, ri, pi, parts, cg, done))) return e;
+      if ((e = hop_oe_xr(dg(c), lprec, qin, tin, xi, ri, pin, parts, cg, done))) return e;
       nb_r = nb_it;
     } else {
       if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
@@ -466,13 +466,16 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
         return e;
       nb_r = nb_blas;
     }
+    // with BF16 operands the search direction is kept in BF16 alone: the
+    // recursion then updates x with the very vector the operator saw
+    void* p = lo16 ? nullptr : pi.p;
     void* plo = lo16 ? pin.p : nullptr;
     const int plo_prec = lo16 ? P_BF16 : P_F32;
     if ((i + 1) % kRuStride != 0)
-      return launch_cg_beta_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st);
+      return launch_cg_beta_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st);
     if ((e = launch_cg_beta(cg, parts, nb_r, N, st))) return e;
     if ((e = reliable_update())) return e;
-    return launch_cg_p(pi.p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st);
+    return launch_cg_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st);
   };
   constexpr int K = 10 * kRuStride;      // iterations per chunk (host poll / graph)
   constexpr int K_TAIL = 2 * kRuStride;  // chunk length near convergence
