@@ -90,6 +90,7 @@ __global__ void k_cg_setup(CGState* s, const double* b2, const double* eta2, CGS
   c.stall_max = cfg.stall_max;
   c.fp64_from = 0;
   c.ru_drop = 0;
+  for (int j = 0; j < kXWindow; ++j) c.alpha_w[j] = 0.0;
   const bool zero = !(b > 0.0) || !(eta2[r] > 0.0);
   c.done = zero ? 1 : 0;
   c.status = zero ? CG_CONVERGED : CG_RUNNING;
@@ -179,7 +180,7 @@ __global__ void k_cg_xr(SX* x, S* r, const S* __restrict__ p, const S* __restric
 
 // p = r + beta p ; optional low-precision copy of p
 template <typename S, typename SP, typename SL>
-__global__ void k_cg_p(SP* p, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
+__global__ void k_cg_p(const SP* p, SP* pn, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
   const int q = blockIdx.y;
   if (cs[q].done) return;
   using A = typename StoreTraits<S>::acc;
@@ -189,7 +190,7 @@ __global__ void k_cg_p(SP* p, const S* __restrict__ r, long n, long rs, const CG
     const auto p0 = ld(p + o + i);
     const auto rv = ld(r + o + i);
     const cpx<A> pv = {rv.re + beta * (A)p0.re, rv.im + beta * (A)p0.im};
-    st(p + o + i, pv);
+    st(pn + o + i, pv);
     if (plo) st(plo + o + i, pv);
   }
 }
@@ -201,7 +202,7 @@ __global__ void k_cg_p(SP* p, const S* __restrict__ r, long n, long rs, const CG
 // workgroups, which is harmless: done is final here (only the reliable
 // update's finish kernel sets the resumable CG_STALLED).
 template <typename S, typename SP, typename SL>
-__global__ void k_cg_beta_p(SP* p, const S* __restrict__ r, long n, long rs, CGState* cs, SL* plo,
+__global__ void k_cg_beta_p(const SP* p, SP* pn, const S* __restrict__ r, long n, long rs, CGState* cs, SL* plo,
                             const double* partials, int nparts) {
   __shared__ double sh[4];
   const int q = blockIdx.y;
@@ -218,8 +219,35 @@ __global__ void k_cg_beta_p(SP* p, const S* __restrict__ r, long n, long rs, CGS
     const auto p0 = ld(p + o + i);
     const auto rv = ld(r + o + i);
     const cpx<A> pv = {rv.re + beta * (A)p0.re, rv.im + beta * (A)p0.im};
-    st(p + o + i, pv);
+    st(pn + o + i, pv);
     if (plo) st(plo + o + i, pv);
+  }
+}
+
+// x += sum_j alpha_w[j] p_j (the deferred updates of one window), summed in
+// slot order in FP32; a slot whose alpha is 0 (an iteration the rhs skipped)
+// is not read
+__global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long rs, const CGState* cs) {
+  const int q = blockIdx.y;
+  float a[kXWindow];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < kXWindow; ++j) {
+    a[j] = (float)cs[q].alpha_w[j];
+    any = any || a[j] != 0.f;
+  }
+  if (!any) return;
+  const size_t o = (size_t)q * rs, ox = (size_t)q * rsx;
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
+    float2 xv = x[ox + i];
+#pragma unroll
+    for (int j = 0; j < kXWindow; ++j) {
+      if (a[j] == 0.f) continue;  // uniform over the workgroup
+      const auto pv = ld(pw.p[j] + o + i);
+      xv.x += a[j] * pv.re;
+      xv.y += a[j] * pv.im;
+    }
+    x[ox + i] = xv;
   }
 }
 
@@ -390,25 +418,28 @@ hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, co
 }
 
 hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs, const CGState* s,
-                       void* plo, int lo_prec, hipStream_t st) {
+                       void* plo, int lo_prec, hipStream_t st, void* pnext) {
   dim3 grid(blas_nblocks(n), nrhs);
   if (prec == P_F64 && p)
-    k_cg_p<double2, double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
-                                                           (double2*)nullptr);
+    k_cg_p<double2, double2, double2><<<grid, kB, 0, st>>>((const double2*)p, (double2*)p, (const double2*)r, n,
+                                                           rs, s, (double2*)nullptr);
   else if (prec == P_F32 && p && (plo == nullptr || lo_prec == P_F32))
-    k_cg_p<float2, float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (float2*)plo);
+    k_cg_p<float2, float2, float2><<<grid, kB, 0, st>>>((const float2*)p, (float2*)p, (const float2*)r, n, rs, s,
+                                                        (float2*)plo);
   else if (prec == P_F32 && p && plo && lo_prec == P_BF16)
-    k_cg_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s, (bf16x2*)plo);
+    k_cg_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((const float2*)p, (float2*)p, (const float2*)r, n, rs, s,
+                                                        (bf16x2*)plo);
   else if (prec == P_F32 && !p && plo && lo_prec == P_BF16)  // the direction lives in BF16 only
-    k_cg_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((bf16x2*)plo, (const float2*)r, n, rs, s,
-                                                        (bf16x2*)nullptr);
+    k_cg_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((const bf16x2*)plo, (bf16x2*)(pnext ? pnext : plo),
+                                                        (const float2*)r, n, rs, s, (bf16x2*)nullptr);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, int nrhs, CGState* s,
-                            void* plo, int lo_prec, const double* partials, int nparts, hipStream_t st) {
+                            void* plo, int lo_prec, const double* partials, int nparts, hipStream_t st,
+                            void* pnext) {
   // every workgroup re-sums its rhs's partials before streaming p: with many
   // rhs, fewer workgroups per rhs (at least 256, each streaming more) keep
   // that repeated sum small while the whole grid stays as large
@@ -416,19 +447,28 @@ hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, i
   const int nbx = std::min(nb, std::max(256, nb / nrhs));
   dim3 grid(nbx, nrhs);
   if (prec == P_F64 && p)
-    k_cg_beta_p<double2, double2, double2><<<grid, kB, 0, st>>>((double2*)p, (const double2*)r, n, rs, s,
-                                                                (double2*)nullptr, partials, nparts);
+    k_cg_beta_p<double2, double2, double2><<<grid, kB, 0, st>>>((const double2*)p, (double2*)p,
+                                                                (const double2*)r, n, rs, s, (double2*)nullptr,
+                                                                partials, nparts);
   else if (prec == P_F32 && p && (plo == nullptr || lo_prec == P_F32))
-    k_cg_beta_p<float2, float2, float2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s,
-                                                             (float2*)plo, partials, nparts);
+    k_cg_beta_p<float2, float2, float2><<<grid, kB, 0, st>>>((const float2*)p, (float2*)p, (const float2*)r, n,
+                                                             rs, s, (float2*)plo, partials, nparts);
   else if (prec == P_F32 && p && plo && lo_prec == P_BF16)
-    k_cg_beta_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((float2*)p, (const float2*)r, n, rs, s,
-                                                             (bf16x2*)plo, partials, nparts);
+    k_cg_beta_p<float2, float2, bf16x2><<<grid, kB, 0, st>>>((const float2*)p, (float2*)p, (const float2*)r, n,
+                                                             rs, s, (bf16x2*)plo, partials, nparts);
   else if (prec == P_F32 && !p && plo && lo_prec == P_BF16)  // the direction lives in BF16 only
-    k_cg_beta_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((bf16x2*)plo, (const float2*)r, n, rs, s,
-                                                             (bf16x2*)nullptr, partials, nparts);
+    k_cg_beta_p<float2, bf16x2, bf16x2><<<grid, kB, 0, st>>>((const bf16x2*)plo,
+                                                             (bf16x2*)(pnext ? pnext : plo), (const float2*)r,
+                                                             n, rs, s, (bf16x2*)nullptr, partials, nparts);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xflush(float2* x, long rsx, const PWindow& pw, long n, long rs, int nrhs, const CGState* s,
+                            hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  k_cg_xflush<<<grid, kB, 0, st>>>(x, rsx, pw, n, rs, s);
   return hipGetLastError();
 }
 

@@ -547,7 +547,10 @@ __device__ inline bool hop_thread(const HopLaunch& a, ThreadSite& ts, cpx<A> (&v
 __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
   for (int r = blockIdx.x; r < a.nrhs; r += gridDim.x) {
     CGState& c = a.alpha_cg[r];
-    if (c.done) continue;  // uniform over the workgroup
+    if (c.done) {  // uniform over the workgroup
+      if (a.alpha_slot >= 0 && threadIdx.x == 0) c.alpha_w[a.alpha_slot] = 0.0;
+      continue;
+    }
     const double* p = a.alpha_parts + (size_t)r * a.alpha_nparts;
     double acc = 0.0;
     for (int i = threadIdx.x; i < a.alpha_nparts; i += kHopBlock) acc += p[i];
@@ -562,6 +565,7 @@ __device__ inline void fused_alpha(const HopLaunch& a, double* sh) {
       c.pAp = v;
       c.alpha = (v > 0.0) ? c.rr / v : 0.0;
       c.rr_prev = c.rr;
+      if (a.alpha_slot >= 0) c.alpha_w[a.alpha_slot] = c.alpha;
     }
   }
   __syncthreads();
@@ -612,7 +616,8 @@ __global__ __launch_bounds__(kHopBlock) void k_hop(const HopLaunch a) {
 // Ap = g5 (A_ee q + 1/2 H t) computed in registers, every rhs that is not done
 // gets x += alpha p, r -= alpha Ap (x, r of type SV, p of the operator's
 // input type SI: the very vector the operator was applied to) and the
-// per-block |r|^2 partial.  Ap is never stored.
+// per-block |r|^2 partial.  Ap is never stored.  With x null the x update is
+// left to a later flush of the deferred updates.
 template <typename SG, typename SI, typename SV, int NR, int RL, bool SPLIT, bool TM>
 __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
   using A = typename StoreTraits<SG>::acc;
@@ -636,16 +641,21 @@ __global__ __launch_bounds__(kHopBlock) void k_hop_xr(const HopLaunch a) {
       const AV alpha = (AV)alpha_d;
       const size_t o = (size_t)q * a.xr_rs + tix(ts.s, 12) + ts.c0 * kTile,
                    ox = (size_t)q * a.xr_xrs + tix(ts.s, 12) + ts.c0 * kTile;
+      if (xb) {  // uniform over the launch
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          auto pv = ld(pb + o + k * kTile);
+          auto xv = ld(xb + ox + k * kTile);
+          xv.re += (AV)alpha_d * pv.re;
+          xv.im += (AV)alpha_d * pv.im;
+          st(xb + ox + k * kTile, xv);
+        }
+      }
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
-        auto pv = ld(pb + o + k * kTile);
-        auto xv = ld(xb + ox + k * kTile);
         auto rv = ld(rb + o + k * kTile);
-        xv.re += (AV)alpha_d * pv.re;
-        xv.im += (AV)alpha_d * pv.im;
         rv.re -= alpha * (AV)v[r][k].re;
         rv.im -= alpha * (AV)v[r][k].im;
-        st(xb + ox + k * kTile, xv);
         st(rb + o + k * kTile, rv);
         nrm += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
       }

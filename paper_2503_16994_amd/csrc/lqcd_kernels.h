@@ -88,6 +88,7 @@ struct HopLaunch {
   struct CGState* alpha_cg;   // nullptr: no alpha step
   const double* alpha_parts;  // [nrhs][alpha_nparts]
   int alpha_nparts;
+  int alpha_slot;             // >= 0: also record alpha in alpha_w[alpha_slot] (0 for a done rhs)
 };
 
 int hop_nblocks(const HopLaunch& h);
@@ -147,6 +148,11 @@ hipError_t launch_clover(const CloverLaunch& c, hipStream_t st);
 enum CGStatus { CG_RUNNING = 0, CG_CONVERGED = 1, CG_MAXITER = 2, CG_NONFINITE = 3, CG_STALLED = 4 };
 
 // CG control of one right-hand side (device memory)
+// Iterations whose x updates a BF16-operand recursion defers: their alpha
+// (CGState::alpha_w) and search directions are kept, and one flush kernel
+// adds them to x at every reliable-update slot (every kXWindow-th iteration).
+constexpr int kXWindow = 5;
+
 struct CGState {
   double rr;       // |r|^2 of the recursion
   double rr_prev;  // |r|^2 this iteration's alpha divided by (set by alpha, read by beta)
@@ -176,6 +182,7 @@ struct CGState {
   int fp64_from;     // iteration at which the rhs continued in FP64 (0: never)
   int ru_drop;       // the pending reliable update was requested by a drop of |r|^2
                      // (tenfold, or the inner target), not by the iteration count
+  double alpha_w[kXWindow];  // alpha of the deferred x updates, by slot (0: none)
 };
 
 struct CGSetup {
@@ -204,12 +211,21 @@ hipError_t launch_cg_xr(void* x, int xprec, long rsx, void* r, const void* p, co
                         int prec, long n, long rs, int nrhs, const CGState* s, double* partials,
                         hipStream_t st);
 // p = r + beta p, also written to p_lo (precision lo_prec) if given; with p
-// null the direction is kept in p_lo alone (BF16, r FP32): p_lo = r + beta p_lo
+// null the direction is kept in BF16 alone (r FP32): p_next = r + beta p_lo,
+// written to p_next (p_lo itself when p_next is null)
 hipError_t launch_cg_p(void* p, const void* r, int prec, long n, long rs, int nrhs,
-                       const CGState* s, void* p_lo, int lo_prec, hipStream_t st);
+                       const CGState* s, void* p_lo, int lo_prec, hipStream_t st, void* p_next = nullptr);
 // beta step and p update in one launch (nparts |r|^2 partials per rhs)
 hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, int nrhs, CGState* s,
-                            void* p_lo, int lo_prec, const double* partials, int nparts, hipStream_t st);
+                            void* p_lo, int lo_prec, const double* partials, int nparts, hipStream_t st,
+                            void* p_next = nullptr);
+// deferred x updates: x += sum_j alpha_w[j] p_j over the kXWindow BF16
+// directions p_j (slots with alpha_w[j] = 0 are not read); x FP32
+struct PWindow {
+  const bf16x2* p[kXWindow];
+};
+hipError_t launch_cg_xflush(float2* x, long rsx, const PWindow& pw, long n, long rs, int nrhs, const CGState* s,
+                            hipStream_t st);
 // reliable-update kernels (each skips rhs without a pending update)
 hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);

@@ -99,13 +99,16 @@ HopLaunch mk(const Ctl& c, int lprec) {
 }
 
 // out_o = A_oo^{-1} D_oe y_e = A_oo^{-1} (-1/2 H y_e); with alpha_cg the
-// launch also computes the CG alpha of every rhs from alpha_parts
+// launch also computes the CG alpha of every rhs from alpha_parts (and
+// records it in window slot alpha_slot if that is >= 0)
 hipError_t hop_eo(const Ctl& c, int lprec, Vec y, Vec out_o, const int* done, int nr_tile,
-                  CGState* alpha_cg = nullptr, const double* alpha_parts = nullptr, int alpha_nparts = 0) {
+                  CGState* alpha_cg = nullptr, const double* alpha_parts = nullptr, int alpha_nparts = 0,
+                  int alpha_slot = -1) {
   HopLaunch h = mk(c, lprec);
   h.alpha_cg = alpha_cg;
   h.alpha_parts = alpha_parts;
   h.alpha_nparts = alpha_nparts;
+  h.alpha_slot = alpha_slot;
   h.p_out = 1;
   h.in_prec = y.prec;
   h.out_prec = out_o.prec;
@@ -445,17 +448,44 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   // ---- one CG iteration (graph-capturable: kernels only) --------------------
   // eo: hop, hop (+g5, |Dhat p|^2), hop (+alpha), hop fused with the x/r
   // update (+|r|^2), then beta fused with the p update, or, every kRuStride-th
-  // iteration, beta, the reliable-update group and the p update
+  // iteration, beta, the reliable-update group and the p update.
+  // With BF16 operands the x updates of kXWindow iterations are deferred: the
+  // search direction of iteration i lives in window buffer i mod kXWindow,
+  // the p update writes the next buffer, the alpha step records alpha in the
+  // same slot, and the flush before each reliable update adds all of them to
+  // x (chunks and phases start at multiples of kRuStride, so the slot of an
+  // iteration is fixed in a captured graph and every window is whole).
   constexpr int kRuStride = 5;
+  static_assert(kRuStride == kXWindow, "x window = reliable-update stride");
+  Vec pwin[kXWindow];
+  PWindow pw{};
+  if (mixed && ip == LQCD_BF16 && eo) {
+    // the FP32 p and q vectors are not used by BF16-operand iterations; each
+    // holds two BF16 vectors of the same rhs stride
+    bf16x2* spare[4] = {(bf16x2*)m.pl, (bf16x2*)m.pl + (size_t)N * HRS, (bf16x2*)m.ql,
+                        (bf16x2*)m.ql + (size_t)N * HRS};
+    pwin[0] = Vec{m.pb, P_BF16, HRS};
+    for (int j = 1; j < kXWindow; ++j) pwin[j] = Vec{spare[j - 1], P_BF16, HRS};
+    for (int j = 0; j < kXWindow; ++j) pw.p[j] = (const bf16x2*)pwin[j].p;
+    // rhs that finish early leave their later slots unwritten; zeros keep the
+    // hops of partly finished rhs tiles finite
+    LQCD_HIP(launch_fill_zero(m.pl, (size_t)N * HRS * 8, st));
+    LQCD_HIP(launch_fill_zero(m.ql, (size_t)N * HRS * 8, st));
+  }
   auto iteration = [&](int i) -> hipError_t {
     hipError_t e;
     int nb_r;  // |r|^2 partials per rhs
+    const int slot = i % kXWindow;
+    const bool win = lo16 && eo;  // deferred x updates
+    if (win) pin = pwin[slot];
     if (eo) {
       const int nb_it = iter_parts(c, lprec);
       if ((e = hop_eo(c, lprec, pin, tin, done, nr_tile))) return e;
       if ((e = hop_oe(c, lprec, pin, tin, qin, true, parts, done, nr_tile))) return e;
-      if ((e = hop_eo(dg(c), lprec, qin, tin, done, nr_tile, cg, parts, nb_it))) return e;  // + alpha
-      if ((e = hop_oe_xr(dg(c), lprec, qin, tin, xi, ri, pin, parts, cg, done))) return e;
+      if ((e = hop_eo(dg(c), lprec, qin, tin, done, nr_tile, cg, parts, nb_it, win ? slot : -1)))
+        return e;  // + alpha
+      if ((e = hop_oe_xr(dg(c), lprec, qin, tin, win ? Vec{nullptr, P_F32, HRS} : xi, ri, pin, parts, cg, done)))
+        return e;
       nb_r = nb_it;
     } else {
       if ((e = dw_full(c, (const double2*)pin.p, (double2*)qin.p, true, parts, done))) return e;
@@ -470,12 +500,14 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     // recursion then updates x with the very vector the operator saw
     void* p = lo16 ? nullptr : pi.p;
     void* plo = lo16 ? pin.p : nullptr;
+    void* pnext = win ? pwin[(slot + 1) % kXWindow].p : nullptr;
     const int plo_prec = lo16 ? P_BF16 : P_F32;
     if ((i + 1) % kRuStride != 0)
-      return launch_cg_beta_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st);
+      return launch_cg_beta_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st, pnext);
     if ((e = launch_cg_beta(cg, parts, nb_r, N, st))) return e;
+    if (win && (e = launch_cg_xflush(m.xl, HRS, pw, n_vec, HRS, N, cg, st))) return e;
     if ((e = reliable_update())) return e;
-    return launch_cg_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st);
+    return launch_cg_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st, pnext);
   };
   constexpr int K = 10 * kRuStride;      // iterations per chunk (host poll / graph)
   constexpr int K_TAIL = 2 * kRuStride;  // chunk length near convergence
