@@ -178,14 +178,35 @@ __global__ void k_cg_xr(SX* x, S* r, const S* __restrict__ p, const S* __restric
   if (threadIdx.x == 0) partials[(size_t)q * gridDim.x + blockIdx.x] = b;
 }
 
-// p = r + beta p ; optional low-precision copy of p
-template <typename S, typename SP, typename SL>
-__global__ void k_cg_p(const SP* p, SP* pn, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
-  const int q = blockIdx.y;
-  if (cs[q].done) return;
-  using A = typename StoreTraits<S>::acc;
-  const A beta = (A)cs[q].beta;
-  const size_t o = (size_t)q * rs;
+// Four consecutive complex elements per access (16 bytes of BF16, 32 of
+// FP32): the streaming kernels of BF16-operand iterations move whole 16-byte
+// words per lane.  p must be 16-byte aligned (element offsets multiples of 4).
+__device__ inline void ld4(const bf16x2* p, cpx<float> (&v)[4]) {
+  const uint4 w = *reinterpret_cast<const uint4*>(p);
+  const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = {__uint_as_float(u[k] << 16), __uint_as_float(u[k] & 0xffff0000u)};
+}
+__device__ inline void st4(bf16x2* p, const cpx<float> (&v)[4]) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(pack_bf16x2(v[0].re, v[0].im), pack_bf16x2(v[1].re, v[1].im),
+                                            pack_bf16x2(v[2].re, v[2].im), pack_bf16x2(v[3].re, v[3].im));
+}
+__device__ inline void ld4(const float2* p, cpx<float> (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4*>(p), b = *reinterpret_cast<const float4*>(p + 2);
+  v[0] = {a.x, a.y};
+  v[1] = {a.z, a.w};
+  v[2] = {b.x, b.y};
+  v[3] = {b.z, b.w};
+}
+__device__ inline void st4(float2* p, const cpx<float> (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+  *reinterpret_cast<float4*>(p + 2) = make_float4(v[2].re, v[2].im, v[3].re, v[3].im);
+}
+
+// pn = r + beta p over the n elements of one rhs (offset o), and plo = pn if
+// given; p and pn may be the same vector
+template <typename S, typename SP, typename SL, typename A>
+__device__ inline void p_update(const SP* p, SP* pn, const S* r, SL* plo, A beta, size_t o, long n) {
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
     const auto p0 = ld(p + o + i);
     const auto rv = ld(r + o + i);
@@ -193,6 +214,32 @@ __global__ void k_cg_p(const SP* p, SP* pn, const S* __restrict__ r, long n, lon
     st(pn + o + i, pv);
     if (plo) st(plo + o + i, pv);
   }
+}
+// the BF16-only direction of BF16-operand iterations, four elements a lane
+__device__ inline void p_update(const bf16x2* p, bf16x2* pn, const float2* r, bf16x2* plo, float beta, size_t o,
+                                long n) {
+  if (plo != nullptr || (n & 3) != 0 || (o & 3) != 0) {
+    p_update<float2, bf16x2, bf16x2, float>(p, pn, r, plo, beta, o, n);
+    return;
+  }
+  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < (n >> 2); i += (long)gridDim.x * kB) {
+    cpx<float> pv[4], rv[4];
+    ld4(p + o + 4 * i, pv);
+    ld4(r + o + 4 * i, rv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pv[k] = {rv[k].re + beta * pv[k].re, rv[k].im + beta * pv[k].im};
+    st4(pn + o + 4 * i, pv);
+  }
+}
+
+// p = r + beta p ; optional low-precision copy of p
+template <typename S, typename SP, typename SL>
+__global__ void k_cg_p(const SP* p, SP* pn, const S* __restrict__ r, long n, long rs, const CGState* cs, SL* plo) {
+  const int q = blockIdx.y;
+  if (cs[q].done) return;
+  using A = typename StoreTraits<S>::acc;
+  const A beta = (A)cs[q].beta;
+  p_update(p, pn, r, plo, beta, (size_t)q * rs, n);
 }
 
 // beta step fused with p = r + beta p (iterations without a reliable update):
@@ -214,14 +261,7 @@ __global__ void k_cg_beta_p(const SP* p, SP* pn, const S* __restrict__ r, long n
   if (!finite(v)) return;
   using A = typename StoreTraits<S>::acc;
   const A beta = (A)((rr0 > 0.0) ? v / rr0 : 0.0);
-  const size_t o = (size_t)q * rs;
-  for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
-    const auto p0 = ld(p + o + i);
-    const auto rv = ld(r + o + i);
-    const cpx<A> pv = {rv.re + beta * (A)p0.re, rv.im + beta * (A)p0.im};
-    st(pn + o + i, pv);
-    if (plo) st(plo + o + i, pv);
-  }
+  p_update(p, pn, r, plo, beta, (size_t)q * rs, n);
 }
 
 // x += sum_j alpha_w[j] p_j (the deferred updates of one window), summed in
@@ -238,6 +278,25 @@ __global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long 
   }
   if (!any) return;
   const size_t o = (size_t)q * rs, ox = (size_t)q * rsx;
+  if (((n | (long)o | (long)ox) & 3) == 0) {  // four elements a lane
+    for (long i = (long)blockIdx.x * kB + threadIdx.x; i < (n >> 2); i += (long)gridDim.x * kB) {
+      cpx<float> xv[4];
+      ld4(x + ox + 4 * i, xv);
+#pragma unroll
+      for (int j = 0; j < kXWindow; ++j) {
+        if (a[j] == 0.f) continue;  // uniform over the workgroup
+        cpx<float> pv[4];
+        ld4(pw.p[j] + o + 4 * i, pv);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xv[k].re += a[j] * pv[k].re;
+          xv[k].im += a[j] * pv[k].im;
+        }
+      }
+      st4(x + ox + 4 * i, xv);
+    }
+    return;
+  }
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
     float2 xv = x[ox + i];
 #pragma unroll

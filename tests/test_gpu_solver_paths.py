@@ -201,3 +201,46 @@ def test_binding_rejects_bad_arrays(sys8):
         lqcd.solve(s["g"], eta, s["kappa"], s["csw"], x0=torch.cat([eta, eta]))
     with pytest.raises(TypeError):
         lqcd.dw_apply(s["g"], lqcd.dirac(s["kappa"], s["csw"]), eta.real.contiguous())
+
+
+def test_bf16_deferred_x_updates_at_maxiter_and_with_a_finished_column(sys8):
+    """BF16 operands defer the x updates of five iterations to one flush.
+    (a) maxiter = 7 stops the recursion inside a window: the returned psi must
+    hold every update up to the last iteration, so its oracle residual agrees
+    with that of the FP32-operand solve stopped at the same iteration (which
+    updates x every iteration) to within the operators' rounding, while two
+    missing updates would leave it far larger; it also equals
+    info.true_residual.  (b) A batch with an identically zero column (done at
+    setup, its window slots never written) and two columns that converge at
+    different iterations: the zero column stays exactly zero, the others
+    reach 1e-10 by the oracle."""
+    s = sys8
+    print("\n[gpu case] bf16 deferred x updates: maxiter 7", flush=True)
+    eta = inputs.z2_noise(s["L"], seed=8)[None]
+    e = torch.from_numpy(eta).cuda()
+    res = {}
+    for inner in (lqcd.F32, lqcd.BF16):
+        r = lqcd.solve(s["g"], e, s["kappa"], s["csw"], tol=1e-10, maxiter=7, inner_prec=inner,
+                       raise_on_noconv=False)
+        torch.cuda.synchronize()
+        rho = rho_oracle(s["L"], orc.PERIODIC, TH, s["U"], s["A"], eta[0], r.psi.cpu().numpy()[0])
+        print(f"inner {inner}: status {r.status} iters {r.info[0]['iters']} rho(oracle) {rho:.4e} "
+              f"info {r.info[0]['true_residual']:.4e}")
+        assert r.status == lqcd.ENOCONV
+        assert abs(rho - r.info[0]["true_residual"]) <= 1e-9 * rho
+        res[inner] = (r.info[0]["iters"], rho)
+    assert res[lqcd.BF16][0] == res[lqcd.F32][0]
+    assert abs(res[lqcd.BF16][1] / res[lqcd.F32][1] - 1.0) < 0.05
+
+    print("[gpu case] bf16 deferred x updates: zero column", flush=True)
+    eta = np.stack([inputs.z2_noise(s["L"], seed=3), np.zeros(s["lat"].spinor_shape(), np.complex128),
+                    inputs.point_source(s["L"], (1, 2, 3, 4), 2, 1)])
+    r = lqcd.solve(s["g"], torch.from_numpy(eta).cuda(), s["kappa"], s["csw"], tol=1e-10,
+                   inner_prec=lqcd.BF16)
+    psi = r.psi.cpu().numpy()
+    assert r.status == lqcd.OK
+    assert np.all(psi[1] == 0) and r.info[1]["iters"] == 0
+    for j in (0, 2):
+        rho = rho_oracle(s["L"], orc.PERIODIC, TH, s["U"], s["A"], eta[j], psi[j])
+        print(f"rhs {j}: iters {r.info[j]['iters']} rho(oracle) {rho:.3e}")
+        assert rho <= 1e-10
