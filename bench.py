@@ -314,10 +314,12 @@ def main():
     ws12 = lqcd.Workspace(lat, pm, 12)
 
     def tune_mixed(ws, g, d, ip, nrhs):
-        """the tuning of the inner precision and of FP64 (the hops of the
-        reliable updates) for nrhs rhs: from the committed table, else
+        """the tuning of the inner precision, of FP64 (the hops of the
+        reliable updates) and, for BF16, of FP32 (the reliable updates'
+        Dhat^+ for the recursion) for nrhs rhs: from the committed table, else
         autotuned"""
-        for prec in (ip, lqcd.F64):
+        precs = (ip, lqcd.F64) + ((lqcd.F32,) if ip == lqcd.BF16 else ())
+        for prec in precs:
             t = lqcd.tune_cache_find(g, prec, nrhs)
             if t is None:
                 t, _ = lqcd.autotune(g, d, prec, nrhs, ws, stream=stream)

@@ -347,12 +347,12 @@ __global__ void k_ru_sub(const double2* __restrict__ b, const double2* __restric
 }
 
 // step 3 (mixed only): r_lo = (float) r_true
-__global__ void k_ru_copy(const double2* __restrict__ R, long rsR, float2* rl, long rsl, long n,
-                          const CGState* cs) {
+template <typename S>
+__global__ void k_ru_copy(const S* __restrict__ R, long rsR, float2* rl, long rsl, long n, const CGState* cs) {
   const int q = blockIdx.y;
   if (ru_skip(cs[q])) return;
   for (long i = (long)blockIdx.x * kB + threadIdx.x; i < n; i += (long)gridDim.x * kB) {
-    double2 v = R[(size_t)q * rsR + i];
+    const S v = R[(size_t)q * rsR + i];
     rl[(size_t)q * rsl + i] = make_float2((float)v.x, (float)v.y);
   }
 }
@@ -546,7 +546,13 @@ hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, lon
 hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st) {
   dim3 grid(blas_nblocks(n), nrhs);
-  k_ru_copy<<<grid, kB, 0, st>>>(R, rsR, rl, rsl, n, s);
+  k_ru_copy<double2><<<grid, kB, 0, st>>>(R, rsR, rl, rsl, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_ru_copy(const float2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
+                          const CGState* s, hipStream_t st) {
+  dim3 grid(blas_nblocks(n), nrhs);
+  k_ru_copy<float2><<<grid, kB, 0, st>>>(R, rsR, rl, rsl, n, s);
   return hipGetLastError();
 }
 hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r, int n_r,

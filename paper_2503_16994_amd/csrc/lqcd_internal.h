@@ -60,7 +60,7 @@ struct GraphEntry {
   uint64_t gauge_uid;
   int solver, inner_prec, nrhs, chunk;
   double mu;  // twisted mass (a kernel argument of the captured launches)
-  lqcd_tuning tune_inner, tune_f64;
+  lqcd_tuning tune_inner, tune_f64, tune_f32;
   hipGraph_t graph;
   hipGraphExec_t exec;
 };

@@ -231,7 +231,10 @@ hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, in
                           const CGState* s, hipStream_t st);
 hipError_t launch_ru_sub(const double2* b, const double2* y, double2* s_out, long n, long rs,
                          int nrhs, const CGState* s, double* partials, hipStream_t st);
+// rl = R (rounded to FP32) for every rhs with a pending reliable update
 hipError_t launch_ru_copy(const double2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
+                          const CGState* s, hipStream_t st);
+hipError_t launch_ru_copy(const float2* R, long rsR, float2* rl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);
 hipError_t launch_ru_finish(CGState* s, const double* part_res, int n_res, const double* part_r,
                             int n_r, int nrhs, hipStream_t st);

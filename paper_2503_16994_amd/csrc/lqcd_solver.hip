@@ -337,6 +337,12 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
   single_tile(h1);
   const int nb_hop = hop_nparts(h1);
   const int nb_hop_tuned = hop_nparts(mk(c, P_F64));
+  // With FP32 operators at hand, a low-precision phase's reliable update
+  // computes the recursion's new r = Dhat^+ s with them (s itself, and with
+  // it the convergence test, stays FP64): r only has to be as accurate as the
+  // FP32 recursion that continues from it.
+  const bool ru32 = mixed && eo && u->U32 != nullptr && w->m.C32 != nullptr && w->m.Ci32 != nullptr;
+  const int nb_ru32 = ru32 ? iter_parts(c, P_F32) : 0;
 
   LQCD_HIP(launch_pack(g->kg, (const double2*)eta, m.E, P_F64, N, false, st));
   if (x0)
@@ -424,6 +430,19 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, ru_tile))) return e;
       if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, ru_tile))) return e;
       if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, N, cg, parts2, st))) return e;
+      if (lo && ru32) {
+        // s rounded into FP32 scratch, Dhat^+ in the workspace's FP32 tuning,
+        // the result copied into the recursion's r (pending rhs only).  The
+        // scratch vectors are free at this point of an iteration: the FP32
+        // t and Ap, and the FP32 q (FP32 recursion) or the two window slots
+        // kept in the FP32 p (BF16 recursion), which the flush has consumed.
+        const Vec s32{m.apl, P_F32, HRS}, t32{m.tl, P_F32, HRS}, r32{lo16 ? m.pl : m.ql, P_F32, HRS};
+        if ((e = launch_ru_copy(m.AP, FRS, m.apl, HRS, 12 * V2, N, cg, st))) return e;
+        if ((e = hop_eo(dg(c), P_F32, s32, t32, skip_ru, 0))) return e;
+        if ((e = hop_oe(dg(c), P_F32, s32, t32, r32, true, parts, skip_ru, 0))) return e;
+        if ((e = launch_ru_copy((const float2*)r32.p, HRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
+        return launch_ru_finish(cg, parts2, blas_nblocks(12 * V2), parts, nb_ru32, N, st);
+      }
       if ((e = hop_eo(dg(c), P_F64, AP, odd_part(TMP, V2), skip_ru, ru_tile))) return e;
       if ((e = hop_oe(dg(c), P_F64, AP, odd_part(TMP, V2), lo ? Q : R, true, parts, skip_ru, ru_tile))) return e;
       if (lo && (e = launch_ru_copy(m.Q, FRS, m.rl, HRS, 12 * V2, N, cg, st))) return e;
@@ -523,7 +542,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
       for (auto& e : w->graphs)
         if (e.gauge_uid == u->uid && e.solver == prm->solver && e.inner_prec == key_prec && e.nrhs == N &&
             e.chunk == len && e.mu == c.mu && same_tuning(e.tune_inner, w->tune[key_prec]) &&
-            same_tuning(e.tune_f64, w->tune[P_F64]))
+            same_tuning(e.tune_f64, w->tune[P_F64]) && same_tuning(e.tune_f32, w->tune[P_F32]))
           exec = e.exec;
       if (!exec) {
         LQCD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -541,8 +560,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
           (void)hipGraphDestroy(gr);
           return hip_status(e3, "hipGraphInstantiate");
         }
-        w->graphs.push_back(
-            GraphEntry{u->uid, prm->solver, key_prec, N, len, c.mu, w->tune[key_prec], w->tune[P_F64], gr, exec});
+        w->graphs.push_back(GraphEntry{u->uid, prm->solver, key_prec, N, len, c.mu, w->tune[key_prec],
+                                       w->tune[P_F64], w->tune[P_F32], gr, exec});
       }
       LQCD_HIP(hipGraphLaunch(exec, st));
       return LQCD_OK;
