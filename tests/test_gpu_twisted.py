@@ -115,11 +115,15 @@ def test_twisted_eo_and_full_cg(c):
             assert rho <= 1e-10
 
 
-@pytest.mark.parametrize("inner", [lqcd.F32, lqcd.BF16], ids=["f32", "bf16"])
-def test_twisted_mixed_multi_rhs_and_batch_equality(inner):
+@pytest.mark.parametrize("inner,pm", [(lqcd.F32, PMASK[lqcd.F32]), (lqcd.BF16, PMASK[lqcd.BF16]),
+                                      (lqcd.BF16, lqcd.PM_F64 | lqcd.PM_F32 | lqcd.PM_BF16)],
+                         ids=["f32", "bf16", "bf16-with-fp32-operators"])
+def test_twisted_mixed_multi_rhs_and_batch_equality(inner, pm):
     """12 point sources in one mixed solve with mu: every column within tol of
-    the oracle, and equal bit for bit to the same column solved alone."""
-    s = TM((8, 8, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=3, pm=PMASK[inner] | lqcd.PM_TWO_ROW)
+    the oracle, and equal bit for bit to the same column solved alone.  With
+    FP32 operators stored beside the BF16 ones, the reliable updates of the
+    BF16 recursion take their Dhat^+ s from the FP32 twisted-mass hops."""
+    s = TM((8, 8, 8, 8), P, TH_AP, 0.2, 0.134, 1.9, 1.0, seed=3, pm=pm | lqcd.PM_TWO_ROW)
     eta = torch.from_numpy(inputs.point_sources_12(s.L, (0, 0, 0, 0))).cuda()
     r = lqcd.solve(s.gauge, eta, s.kappa, s.csw, tol=1e-10, inner_prec=inner, maxiter=20000, mu=s.mu)
     assert r.status == lqcd.OK
