@@ -264,10 +264,15 @@ __global__ void k_cg_beta_p(const SP* p, SP* pn, const S* __restrict__ r, long n
   p_update(p, pn, r, plo, beta, (size_t)q * rs, n);
 }
 
+__device__ inline bool ru_skip(const CGState& c) { return c.skip_ru != 0 || c.done != 0; }
+
 // x += sum_j alpha_w[j] p_j (the deferred updates of one window), summed in
 // slot order in FP32; a slot whose alpha is 0 (an iteration the rhs skipped)
-// is not read
-__global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long rs, const CGState* cs) {
+// is not read.  With X given, a rhs with a pending reliable update also gets
+// the update's first step here: X += x (FP64), x = 0, so that x is not
+// written and read back in between.
+__global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long rs, const CGState* cs,
+                            double2* X, long rsX) {
   const int q = blockIdx.y;
   float a[kXWindow];
   bool any = false;
@@ -276,8 +281,9 @@ __global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long 
     a[j] = (float)cs[q].alpha_w[j];
     any = any || a[j] != 0.f;
   }
-  if (!any) return;
-  const size_t o = (size_t)q * rs, ox = (size_t)q * rsx;
+  const bool fold = X != nullptr && !ru_skip(cs[q]);
+  if (!any && !fold) return;
+  const size_t o = (size_t)q * rs, ox = (size_t)q * rsx, oX = (size_t)q * rsX;
   if (((n | (long)o | (long)ox) & 3) == 0) {  // four elements a lane
     for (long i = (long)blockIdx.x * kB + threadIdx.x; i < (n >> 2); i += (long)gridDim.x * kB) {
       cpx<float> xv[4];
@@ -293,6 +299,15 @@ __global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long 
           xv[k].im += a[j] * pv[k].im;
         }
       }
+      if (fold) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double2* xp = X + oX + 4 * i + k;
+          const double2 b = *xp;
+          *xp = make_double2(b.x + (double)xv[k].re, b.y + (double)xv[k].im);
+          xv[k] = {0.f, 0.f};
+        }
+      }
       st4(x + ox + 4 * i, xv);
     }
     return;
@@ -306,11 +321,14 @@ __global__ void k_cg_xflush(float2* x, long rsx, const PWindow pw, long n, long 
       xv.x += a[j] * pv.re;
       xv.y += a[j] * pv.im;
     }
+    if (fold) {
+      const double2 b = X[oX + i];
+      X[oX + i] = make_double2(b.x + (double)xv.x, b.y + (double)xv.y);
+      xv = make_float2(0.f, 0.f);
+    }
     x[ox + i] = xv;
   }
 }
-
-__device__ inline bool ru_skip(const CGState& c) { return c.skip_ru != 0 || c.done != 0; }
 
 // reliable update, step 1: fold the low-precision correction into x (FP64)
 __global__ void k_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, const CGState* cs) {
@@ -525,9 +543,9 @@ hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, i
 }
 
 hipError_t launch_cg_xflush(float2* x, long rsx, const PWindow& pw, long n, long rs, int nrhs, const CGState* s,
-                            hipStream_t st) {
+                            hipStream_t st, double2* X, long rsX) {
   dim3 grid(blas_nblocks(n), nrhs);
-  k_cg_xflush<<<grid, kB, 0, st>>>(x, rsx, pw, n, rs, s);
+  k_cg_xflush<<<grid, kB, 0, st>>>(x, rsx, pw, n, rs, s, X, rsX);
   return hipGetLastError();
 }
 

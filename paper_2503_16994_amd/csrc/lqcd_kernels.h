@@ -220,12 +220,14 @@ hipError_t launch_cg_beta_p(void* p, const void* r, int prec, long n, long rs, i
                             void* p_lo, int lo_prec, const double* partials, int nparts, hipStream_t st,
                             void* p_next = nullptr);
 // deferred x updates: x += sum_j alpha_w[j] p_j over the kXWindow BF16
-// directions p_j (slots with alpha_w[j] = 0 are not read); x FP32
+// directions p_j (slots with alpha_w[j] = 0 are not read); x FP32.  With X
+// (FP64) given, every rhs with a pending reliable update then also has x
+// folded into X and zeroed (the update's fold step).
 struct PWindow {
   const bf16x2* p[kXWindow];
 };
 hipError_t launch_cg_xflush(float2* x, long rsx, const PWindow& pw, long n, long rs, int nrhs, const CGState* s,
-                            hipStream_t st);
+                            hipStream_t st, double2* X = nullptr, long rsX = 0);
 // reliable-update kernels (each skips rhs without a pending update)
 hipError_t launch_ru_fold(double2* X, long rsX, float2* xl, long rsl, long n, int nrhs,
                           const CGState* s, hipStream_t st);

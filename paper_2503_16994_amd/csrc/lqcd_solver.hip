@@ -426,7 +426,8 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     if (eo) {
       const int ru_tile = lo ? 0 : 1;
       const int nb_ru = lo ? nb_hop_tuned : nb_hop;
-      if (lo && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
+      // (with deferred x updates the flush before the update has folded x)
+      if (lo && !lo16 && (e = launch_ru_fold(m.X, FRS, m.xl, HRS, 12 * V2, N, cg, st))) return e;
       if ((e = hop_eo(c, P_F64, X, odd_part(TMP, V2), skip_ru, ru_tile))) return e;
       if ((e = hop_oe(c, P_F64, X, odd_part(TMP, V2), Q, false, nullptr, skip_ru, ru_tile))) return e;
       if ((e = launch_ru_sub(m.EH, m.Q, m.AP, 12 * V2, FRS, N, cg, parts2, st))) return e;
@@ -524,7 +525,7 @@ extern "C" int lqcd_solve(const lqcd_gauge_t* u, const lqcd_solve_params* prm, c
     if ((i + 1) % kRuStride != 0)
       return launch_cg_beta_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, parts, nb_r, st, pnext);
     if ((e = launch_cg_beta(cg, parts, nb_r, N, st))) return e;
-    if (win && (e = launch_cg_xflush(m.xl, HRS, pw, n_vec, HRS, N, cg, st))) return e;
+    if (win && (e = launch_cg_xflush(m.xl, HRS, pw, n_vec, HRS, N, cg, st, m.X, FRS))) return e;
     if ((e = reliable_update())) return e;
     return launch_cg_p(p, ri.p, pi.prec, n_vec, pi.rs, N, cg, plo, plo_prec, st, pnext);
   };
