@@ -32,10 +32,6 @@ constexpr int kMesonChunk = 256;  // sites per workgroup
 
 using cd = cpx<double>;
 
-__device__ inline cd cmulc_b(cd a, cd b) {  // a * conj(b)
-  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
-}
-
 __global__ __launch_bounds__(kMesonBlock) void k_meson_partial(const double2* __restrict__ psi, long V, long V3,
                                                                int nchunk, double2* partials) {
   __shared__ double2 S[kMesonPass][12][12];  // [site][row al a][col be c]
@@ -74,7 +70,8 @@ __global__ __launch_bounds__(kMesonBlock) void k_meson_partial(const double2* __
 #pragma unroll
         for (int be = 0; be < 4; ++be)
 #pragma unroll
-          for (int be2 = 0; be2 < 4; ++be2) acc[be][be2] = cadd(acc[be][be2], cmulc_b(r1[3 * be + c], r2[3 * be2 + c]));
+          for (int be2 = 0; be2 < 4; ++be2)
+            acc[be][be2] = cmacc(acc[be][be2], r2[3 * be2 + c], r1[3 * be + c]);  // += r1 conj(r2), four FMAs
     }
     __syncthreads();
   }
