@@ -6,8 +6,10 @@ exp(i 0.2 H) (Gaussian traceless Hermitian H, seed 3), periodic space /
 antiperiodic time, kappa = 0.135, csw = 1.9, the 12 spin-colour point
 sources at the origin solved together as one 12-rhs even-odd preconditioned
 CG with BF16-storage operands (links, clover blocks and the iterated
-spinors in BF16, FP32 arithmetic) and FP64 reliable updates every 100
-iterations, to a true relative residual of 1e-10 recomputed in FP64.  Each
+spinors in BF16, FP32 arithmetic) and reliable updates (true residual in
+FP64, the recursion's restart residual through the FP32 operators) on a
+tenfold drop of |r| and at least every 100 iterations, to a true relative
+residual of 1e-10 recomputed in FP64.  Each
 step runs the whole path: clover term (built once per gauge field and
 parameters, then cached), source preparation, CG on Dhat^+ Dhat in hipGraph
 chunks, odd-site reconstruction and the FP64 full-lattice residual check.
@@ -427,7 +429,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "32^3x64 Wilson-clover propagator: the 12 point sources at the origin in one "
                                "12-rhs even-odd CG, BF16-storage operands with FP32 arithmetic, FP64 reliable "
-                               "updates every 100 iterations, true residual 1e-10",
+                               "updates (on a tenfold drop of |r|, at least every 100 iterations), true residual "
+                               "1e-10",
                    "lattice": list(L), "kappa": KAPPA_STEP, "csw": CSW, "bc": "periodic/antiperiodic",
                    "link_eps": EPS, "link_seed": SEED_STEP, "sources": 12, "tol": TOL,
                    "storage": "bf16 (links, clover, p/q/t spinors); f32 recursion; f64 solution and residuals",
