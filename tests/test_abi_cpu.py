@@ -187,6 +187,27 @@ def test_tuning_cache_file_round_trip(tmp_path):
     assert lqcd.tune_cache_size() == 0
 
 
+def test_committed_tuning_table_loads():
+    """The measured tuning table that ships with the package (read by the
+    benchmark) is valid cache input: every data line loads, one entry per
+    distinct key, and it holds the kernels of the 32^3x64 benchmark step
+    (BF16, FP32 and FP64 at 12 rhs, FP64 at one rhs)."""
+    from paper_2503_16994_amd import lqcd
+    import os
+    path = os.path.join(os.path.dirname(lqcd.__file__), "tuning", "gfx950.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    keys = {tuple(r[:11]) for r in rows}
+    lqcd.tune_cache_clear()
+    try:
+        lqcd.tune_cache_load(path)
+        assert lqcd.tune_cache_size() == len(keys)
+    finally:
+        lqcd.tune_cache_clear()
+    step = {(r[7], r[8]) for r in rows if r[1:5] == ["32", "32", "32", "64"] and r[9] == "0"}
+    assert {("2", "12"), ("1", "12"), ("0", "12"), ("0", "1")} <= step
+    assert all(float(r[15]) > 0 for r in rows)
+
+
 def test_binding_argument_checks_without_a_gpu():
     """The binding's checks of spinor arguments run before any pointer
     crosses the ABI (here on CPU tensors: they fail as not on the device)."""
